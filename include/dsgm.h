@@ -1,0 +1,179 @@
+/*
+ * dsgm.h -- C ABI of libdsgm.so: the Dual-Mode Single Gaussian Model (DSGM)
+ * background update and foreground mask on an MI355X (gfx950) GPU.
+ *
+ * Method: Henderson & Vertescher, "An Analysis of Parallelized Motion Masking
+ * Using Dual-Mode Single Gaussian Models" (arXiv:1702.05156):
+ *   Sec. 2.2  Single Gaussian Model: per pixel, the mean and the variance are
+ *             blended with the new intensity at an age-dependent rate and the
+ *             age grows by one up to a cap of 30 (grid of one pixel, so the
+ *             block mean is the pixel's intensity).
+ *   Sec. 2.3  Dual-mode SGM: an apparent model A and a candidate model C; test
+ *             A, then C, update the one that matches, else reset C; promote C
+ *             to A when it is older.
+ *   Appendix  "Dual-mode SGM Inner Update Code Snippet": the variance floor in
+ *             the match tests and the 0/255 foreground rule.
+ *   Sec. 3.4  the parallel decomposition: pixels are independent.
+ *
+ * Conventions
+ *   - Every pointer argument is a DEVICE pointer unless marked (host).  The
+ *     caller owns all memory; no call allocates device memory.
+ *   - Element strides: frames and every per-frame output (masks, bg, codes,
+ *     gradients of frames and of bg) are T x H x W arrays addressed as
+ *     t*frame_stride + h*row_stride + w, in elements of their own type.  State
+ *     planes and their gradients are dense H x W (pitch W).
+ *   - Every call is asynchronous on `stream` (NULL = the null stream) and never
+ *     synchronizes.  Arguments are validated on the host before any HIP call; a
+ *     kernel fault surfaces as a HIP error of a later call or synchronization.
+ *   - Every call returns a dsgm_status; nothing is thrown across the ABI.  On
+ *     failure dsgm_last_error() (per thread) describes it.
+ *   - Calls are reentrant; concurrent calls on different streams that touch
+ *     disjoint memory are independent.
+ *   - NaN or infinite intensities are not supported: results are whatever the
+ *     IEEE comparisons make of them (memory safety is unaffected).
+ */
+#ifndef DSGM_H
+#define DSGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DSGM_OK = 0,
+  DSGM_E_ARG = -1,         /* null pointer, bad enum or bad parameter value   */
+  DSGM_E_SHAPE = -2,       /* negative size, stride too small, too large      */
+  DSGM_E_DTYPE = -3,       /* unsupported storage/accumulation combination    */
+  DSGM_E_ALIGN = -4,       /* pointer not aligned to its element size         */
+  DSGM_E_WORKSPACE = -5,   /* workspace/checkpoint buffer too small           */
+  DSGM_E_HIP = -6,         /* the HIP runtime reported an error               */
+  DSGM_E_UNSUPPORTED = -7  /* valid but not implemented                       */
+} dsgm_status;
+
+/* storage type of the frames */
+typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2 } dsgm_in_dtype;
+
+/* type of the model state and of every arithmetic operation.  Supported:
+ * F64 with F64/F32/BF16 frames; F32 with F32/BF16 frames. */
+typedef enum { DSGM_ACC_F64 = 0, DSGM_ACC_F32 = 1 } dsgm_acc;
+
+/* learning weight of a model of age a: Sec. 2.2 gives 1/(a+1); the appendix
+ * computes 1/a.  The complementary weight is 1 - w in the accumulation type. */
+typedef enum { DSGM_WEIGHT_EQ = 0, DSGM_WEIGHT_APPENDIX = 1 } dsgm_weight_rule;
+
+/* background rule (appendix): (mean_A - x)^2 <= theta_d * max(mask_floor, ref)
+ * with ref = var_A (VARIANCE) or ref = x as printed (PRINTED). */
+typedef enum { DSGM_MASK_VARIANCE = 0, DSGM_MASK_PRINTED = 1 } dsgm_mask_rule;
+
+/* decision-code bits written per pixel and frame by dsgm_forward(codes != NULL) */
+enum { DSGM_CODE_HIT_A = 1, DSGM_CODE_HIT_C = 2, DSGM_CODE_RESET = 4, DSGM_CODE_SWAP = 8,
+       DSGM_CODE_FG = 16 };
+
+typedef struct {
+  double theta_s;     /* match: (x - mean)^2 < theta_s * max(var, var_floor), >= 0 */
+  double theta_d;     /* background threshold, >= 0                               */
+  double var_init;    /* variance of a reset candidate (255 on 8-bit data), >= 0  */
+  double var_floor;   /* appendix floor inside the match tests (0.1 on 8-bit)     */
+  double mask_floor;  /* appendix floor inside the background rule (0.25)         */
+  int32_t age_max;    /* age cap, 1..255 (30 in Sec. 2.2)                         */
+  int32_t weight_rule;/* dsgm_weight_rule                                         */
+  int32_t mask_rule;  /* dsgm_mask_rule                                           */
+} dsgm_params;
+
+typedef struct {
+  int64_t T, H, W;      /* frames, rows, columns (each >= 0)                       */
+  int64_t row_stride;   /* elements between rows, >= W                             */
+  int64_t frame_stride; /* elements between frames, >= (H-1)*row_stride + W        */
+} dsgm_shape;
+
+/* model state: four H x W planes of the accumulation type and two H x W uint8
+ * age planes; ages must lie in [1, age_max] */
+typedef struct {
+  void* mean_a;
+  void* var_a;
+  void* mean_c;
+  void* var_c;
+  uint8_t* age_a;
+  uint8_t* age_c;
+} dsgm_state;
+
+/* gradients of the four float state planes (H x W each, accumulation type) */
+typedef struct {
+  void* mean_a;
+  void* var_a;
+  void* mean_c;
+  void* var_c;
+} dsgm_grad_state;
+
+/*
+ * The paper's constants on an intensity scale of width `intensity_range`
+ * (255 for 8-bit data, 2 for data in [-1, 1)): var_init = 255 s^2 (Sec. 2.3),
+ * age_max = 30 (Sec. 2.2), var_floor = 0.1 s^2 and mask_floor = 0.25 s^2 for
+ * the VARIANCE rule or 0.25 s for the PRINTED rule (appendix), s = range/255.
+ * theta_s = 2 and theta_d = 4 (not printed in the paper).  `p` is a host
+ * pointer.  Returns DSGM_E_ARG for a NULL p, a non-positive range or a bad rule.
+ */
+int dsgm_params_default(dsgm_params* p /* host */, double intensity_range, int32_t mask_rule);
+
+/*
+ * Initial model from one frame (the paper states none): mean_a = mean_c = x,
+ * var_a = var_c = var_init, age_a = age_c = 1.  `frame0` is an H x W frame
+ * addressed with shape.row_stride (shape.T and frame_stride are ignored).
+ */
+int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                               dsgm_acc acc, const dsgm_params* params /* host */,
+                               dsgm_state* state /* host struct of device pointers */,
+                               hipStream_t stream);
+
+/*
+ * Run T frames of the DSGM update (Sec. 2.2-2.3, appendix) over every pixel,
+ * updating `state` in place.  T == 1 is the per-frame streaming step; T > 1
+ * fuses the frames, keeping each pixel's model in registers, with results
+ * bit-identical to T calls with T == 1.
+ *   masks      T x H x W uint8, 0 = background, 255 = foreground (required)
+ *   bg         T x H x W of the accumulation type: mean_A after each frame
+ *              (optional, NULL to skip)
+ *   ckpt       checkpoint buffer of dsgm_ckpt_bytes(shape, acc, ckpt_every)
+ *              bytes: the state before frames 0, K, 2K, ... (K = ckpt_every),
+ *              used by dsgm_backward (optional, NULL to skip)
+ *   codes      T x H x W uint8 decision codes (DSGM_CODE_* bits; optional)
+ * With ACC_F64 the arithmetic is IEEE binary64, rounded after every operation
+ * (no fused multiply-add), and the results are bit-identical to a scalar FP64
+ * evaluation of the same steps.
+ */
+int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
+                 const dsgm_params* params /* host */, dsgm_state* state /* host struct */,
+                 uint8_t* masks, void* bg, void* ckpt, int32_t ckpt_every, uint8_t* codes,
+                 hipStream_t stream);
+
+/* bytes of the checkpoint buffer for dsgm_forward/dsgm_backward (0 on bad args) */
+size_t dsgm_ckpt_bytes(dsgm_shape shape, dsgm_acc acc, int32_t ckpt_every);
+
+/* human-readable name of a status code (static string) */
+const char* dsgm_status_string(int status);
+
+/* description of the last failure of a call on this thread ("" if none) */
+const char* dsgm_last_error(void);
+
+/* ABI version: major*10000 + minor*100 + patch */
+int dsgm_version(void);
+
+/*
+ * Launch-shape override for tuning and tests (process-wide): `block` threads
+ * per workgroup (0 = default, else a multiple of 64 in 64..256) and `vector`
+ * pixels per lane (0 = the widest that sizes, strides and alignments allow,
+ * else 1, 2 or 4; a value the arguments do not allow is ignored).  Results do
+ * not depend on either.  Returns DSGM_E_ARG for other values.
+ */
+int dsgm_set_launch(int32_t block, int32_t vector);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSGM_H */

@@ -1,0 +1,273 @@
+// dsgm_api.hip -- the extern "C" entry points of libdsgm.so declared in
+// include/dsgm.h: argument validation (host only, before any HIP call), launch
+// configuration and dispatch to the kernels.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+
+#include "dsgm.h"
+#include "dsgm_internal.h"
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+int fail(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int ok() {
+  g_last_error[0] = '\0';
+  return DSGM_OK;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(DSGM_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+size_t in_size(int d) { return d == DSGM_IN_F64 ? 8 : d == DSGM_IN_F32 ? 4 : 2; }
+size_t acc_size(int a) { return a == DSGM_ACC_F64 ? 8 : 4; }
+
+bool aligned(const void* p, size_t n) { return (reinterpret_cast<uintptr_t>(p) % n) == 0; }
+
+int64_t pad256(int64_t b) { return (b + 255) / 256 * 256; }
+
+int check_params(const dsgm_params* p) {
+  if (!p) return fail(DSGM_E_ARG, "params is NULL");
+  const double v[5] = {p->theta_s, p->theta_d, p->var_init, p->var_floor, p->mask_floor};
+  const char* n[5] = {"theta_s", "theta_d", "var_init", "var_floor", "mask_floor"};
+  for (int i = 0; i < 5; ++i) {
+    if (std::isnan(v[i])) return fail(DSGM_E_ARG, "params.%s is NaN", n[i]);
+    if (i != 4 && v[i] < 0) return fail(DSGM_E_ARG, "params.%s < 0", n[i]);
+  }
+  if (std::isinf(p->var_init) || std::isinf(p->var_floor) || std::isinf(p->mask_floor))
+    return fail(DSGM_E_ARG, "params: var_init and the floors must be finite");
+  if (p->age_max < 1 || p->age_max > 255)
+    return fail(DSGM_E_ARG, "params.age_max = %d outside 1..255", p->age_max);
+  if (p->weight_rule != DSGM_WEIGHT_EQ && p->weight_rule != DSGM_WEIGHT_APPENDIX)
+    return fail(DSGM_E_ARG, "params.weight_rule = %d invalid", p->weight_rule);
+  if (p->mask_rule != DSGM_MASK_VARIANCE && p->mask_rule != DSGM_MASK_PRINTED)
+    return fail(DSGM_E_ARG, "params.mask_rule = %d invalid", p->mask_rule);
+  return DSGM_OK;
+}
+
+int check_types(int in_dtype, int acc) {
+  if (in_dtype < DSGM_IN_F64 || in_dtype > DSGM_IN_BF16)
+    return fail(DSGM_E_DTYPE, "in_dtype = %d invalid", in_dtype);
+  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32) return fail(DSGM_E_DTYPE, "acc = %d invalid", acc);
+  if (acc == DSGM_ACC_F32 && in_dtype == DSGM_IN_F64)
+    return fail(DSGM_E_DTYPE, "F64 frames with F32 accumulation is not supported");
+  return DSGM_OK;
+}
+
+// frames-like arrays: per-frame extent must fit 31 bits of elements and bytes
+int check_shape(const dsgm_shape& s, size_t max_elem_bytes) {
+  if (s.T < 0 || s.H < 0 || s.W < 0)
+    return fail(DSGM_E_SHAPE, "negative size T=%lld H=%lld W=%lld", (long long)s.T,
+                (long long)s.H, (long long)s.W);
+  if (s.row_stride < s.W)
+    return fail(DSGM_E_SHAPE, "row_stride %lld < W %lld", (long long)s.row_stride, (long long)s.W);
+  const int64_t extent = s.H > 0 ? (s.H - 1) * s.row_stride + s.W : 0;
+  if (s.T > 1 && s.frame_stride < extent)
+    return fail(DSGM_E_SHAPE, "frame_stride %lld < frame extent %lld", (long long)s.frame_stride,
+                (long long)extent);
+  if (s.frame_stride < 0) return fail(DSGM_E_SHAPE, "negative frame_stride");
+  if (double(extent) * double(max_elem_bytes) >= 2147483648.0)
+    return fail(DSGM_E_SHAPE, "one frame spans %lld elements: more than 2^31 bytes",
+                (long long)extent);
+  if (s.H > 0 && s.W > 0 && double(s.H) * double(s.W) >= 2147483648.0)
+    return fail(DSGM_E_SHAPE, "H*W >= 2^31");
+  return DSGM_OK;
+}
+
+// widest per-lane pixel count allowed by the sizes, strides and alignments
+int pick_vector(const dsgm_shape& s, const void* const* ptrs, const size_t* elem, int n) {
+  const int cand[3] = {4, 2, 1};
+  for (int c : cand) {
+    if (s.W % c || s.row_stride % c || (s.T > 1 && s.frame_stride % c)) continue;
+    bool good = true;
+    for (int i = 0; i < n && good; ++i)
+      if (ptrs[i] && !aligned(ptrs[i], elem[i] * c)) good = false;
+    if (good) return c;
+  }
+  return 1;
+}
+
+int g_block_override = 0;  // set by dsgm_set_launch (tuning)
+int g_vector_override = 0;
+
+}  // namespace
+
+extern "C" {
+
+int dsgm_version(void) { return 100; }
+
+const char* dsgm_status_string(int status) {
+  switch (status) {
+    case DSGM_OK: return "DSGM_OK";
+    case DSGM_E_ARG: return "DSGM_E_ARG";
+    case DSGM_E_SHAPE: return "DSGM_E_SHAPE";
+    case DSGM_E_DTYPE: return "DSGM_E_DTYPE";
+    case DSGM_E_ALIGN: return "DSGM_E_ALIGN";
+    case DSGM_E_WORKSPACE: return "DSGM_E_WORKSPACE";
+    case DSGM_E_HIP: return "DSGM_E_HIP";
+    case DSGM_E_UNSUPPORTED: return "DSGM_E_UNSUPPORTED";
+    default: return "DSGM_UNKNOWN";
+  }
+}
+
+const char* dsgm_last_error(void) { return g_last_error; }
+
+int dsgm_params_default(dsgm_params* p, double intensity_range, int32_t mask_rule) {
+  if (!p) return fail(DSGM_E_ARG, "params is NULL");
+  if (!(intensity_range > 0) || std::isinf(intensity_range))
+    return fail(DSGM_E_ARG, "intensity_range must be positive and finite");
+  if (mask_rule != DSGM_MASK_VARIANCE && mask_rule != DSGM_MASK_PRINTED)
+    return fail(DSGM_E_ARG, "mask_rule = %d invalid", mask_rule);
+  const double s = intensity_range / 255.0;
+  p->theta_s = 2.0;
+  p->theta_d = 4.0;
+  p->var_init = 255.0 * s * s;
+  p->var_floor = 0.1 * s * s;
+  p->mask_floor = mask_rule == DSGM_MASK_VARIANCE ? 0.25 * s * s : 0.25 * s;
+  p->age_max = 30;
+  p->weight_rule = DSGM_WEIGHT_EQ;
+  p->mask_rule = mask_rule;
+  return ok();
+}
+
+size_t dsgm_ckpt_bytes(dsgm_shape shape, dsgm_acc acc, int32_t ckpt_every) {
+  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32) return 0;
+  if (ckpt_every < 1 || shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;
+  const int64_t n = (shape.T + ckpt_every - 1) / ckpt_every;
+  const int64_t px = shape.H * shape.W;
+  const int64_t slot = 4 * pad256(px * int64_t(acc_size(acc))) + 2 * pad256(px);
+  return size_t(n * slot);
+}
+
+int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                               dsgm_acc acc, const dsgm_params* params, dsgm_state* state,
+                               hipStream_t stream) {
+  int rc;
+  if ((rc = check_types(in_dtype, acc))) return rc;
+  if ((rc = check_params(params))) return rc;
+  dsgm_shape one = shape;
+  one.T = 1;
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc);
+  if ((rc = check_shape(one, ie > ae ? ie : ae))) return rc;
+  if (!state) return fail(DSGM_E_ARG, "state is NULL");
+  const int64_t px = shape.H * shape.W;
+  if (px == 0) return ok();
+  if (!frame0) return fail(DSGM_E_ARG, "frame0 is NULL");
+  if (!state->mean_a || !state->var_a || !state->mean_c || !state->var_c || !state->age_a ||
+      !state->age_c)
+    return fail(DSGM_E_ARG, "a state plane is NULL");
+  const void* ptrs[5] = {frame0, state->mean_a, state->var_a, state->mean_c, state->var_c};
+  const size_t elem[5] = {ie, ae, ae, ae, ae};
+  for (int i = 0; i < 5; ++i)
+    if (!aligned(ptrs[i], elem[i]))
+      return fail(DSGM_E_ALIGN, "pointer argument %d is not aligned to %zu bytes", i, elem[i]);
+  dsgm::FwdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.frames = frame0;
+  a.mean_a = state->mean_a;
+  a.var_a = state->var_a;
+  a.mean_c = state->mean_c;
+  a.var_c = state->var_c;
+  a.age_a = state->age_a;
+  a.age_c = state->age_c;
+  a.H = shape.H;
+  a.W = shape.W;
+  a.row_stride = shape.row_stride;
+  a.var_init = params->var_init;
+  hipError_t e = dsgm::launch_init(a, in_dtype, acc, stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_state_init_from_frame launch");
+  return ok();
+}
+
+int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
+                 const dsgm_params* params, dsgm_state* state, uint8_t* masks, void* bg,
+                 void* ckpt, int32_t ckpt_every, uint8_t* codes, hipStream_t stream) {
+  int rc;
+  if ((rc = check_types(in_dtype, acc))) return rc;
+  if ((rc = check_params(params))) return rc;
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc);
+  if ((rc = check_shape(shape, ie > ae ? ie : ae))) return rc;
+  if (!state) return fail(DSGM_E_ARG, "state is NULL");
+  const int64_t px = shape.H * shape.W;
+  if (px == 0 || shape.T == 0) return ok();
+  if (!frames) return fail(DSGM_E_ARG, "frames is NULL");
+  if (!masks) return fail(DSGM_E_ARG, "masks is NULL");
+  if (!state->mean_a || !state->var_a || !state->mean_c || !state->var_c || !state->age_a ||
+      !state->age_c)
+    return fail(DSGM_E_ARG, "a state plane is NULL");
+  if (ckpt && ckpt_every < 1) return fail(DSGM_E_ARG, "ckpt_every = %d < 1", ckpt_every);
+  const void* ptrs[11] = {frames, masks, bg, codes, state->mean_a, state->var_a,
+                          state->mean_c, state->var_c, state->age_a, state->age_c, ckpt};
+  const size_t elem[11] = {ie, 1, ae, 1, ae, ae, ae, ae, 1, 1, 256};
+  for (int i = 0; i < 11; ++i) {
+    const size_t need = i == 10 ? 16 : elem[i];
+    if (ptrs[i] && !aligned(ptrs[i], need))
+      return fail(DSGM_E_ALIGN, "pointer argument %d is not aligned to %zu bytes", i, need);
+  }
+  int P = pick_vector(shape, ptrs, elem, 10);
+  if (ckpt && !aligned(ckpt, ae * P)) P = 1;
+  if (g_vector_override && P % g_vector_override == 0) P = g_vector_override;
+
+  dsgm::FwdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.frames = frames;
+  a.masks = masks;
+  a.bg = bg;
+  a.codes = codes;
+  a.mean_a = state->mean_a;
+  a.var_a = state->var_a;
+  a.mean_c = state->mean_c;
+  a.var_c = state->var_c;
+  a.age_a = state->age_a;
+  a.age_c = state->age_c;
+  a.ckpt = ckpt;
+  a.ckpt_every = ckpt ? ckpt_every : 1;
+  a.ckpt_fplane = pad256(px * int64_t(ae));
+  a.ckpt_aplane = pad256(px);
+  a.ckpt_slot_bytes = 4 * a.ckpt_fplane + 2 * a.ckpt_aplane;
+  a.T = shape.T;
+  a.H = shape.H;
+  a.W = shape.W;
+  a.row_stride = shape.row_stride;
+  a.frame_stride = shape.frame_stride;
+  a.groups_per_row = shape.W / P;
+  a.ngroups = shape.H * (shape.W / P);
+  a.theta_s = params->theta_s;
+  a.theta_d = params->theta_d;
+  a.var_init = params->var_init;
+  a.var_floor = params->var_floor;
+  a.mask_floor = params->mask_floor;
+  a.age_max = params->age_max;
+  a.weight_rule = params->weight_rule;
+  a.mask_rule = params->mask_rule;
+  const int block = g_block_override ? g_block_override : 256;
+  hipError_t e = dsgm::launch_forward(a, in_dtype, acc, P, block, stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_forward launch");
+  return ok();
+}
+
+// Launch-shape override used by the tuner and the tests: block size (64..256,
+// multiple of 64, 0 = default) and pixels per lane (1, 2, 4; 0 = widest legal).
+int dsgm_set_launch(int32_t block, int32_t vector) {
+  if (block != 0 && (block < 64 || block > 256 || block % 64))
+    return fail(DSGM_E_ARG, "block = %d: must be 0 or a multiple of 64 in 64..256", block);
+  if (vector != 0 && vector != 1 && vector != 2 && vector != 4)
+    return fail(DSGM_E_ARG, "vector = %d: must be 0, 1, 2 or 4", vector);
+  g_block_override = block;
+  g_vector_override = vector;
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// dsgm_device.h -- device-side pieces shared by the DSGM kernels (internal).
+//
+// One step of the Dual-Mode Single Gaussian Model for one pixel (Henderson &
+// Vertescher, arXiv:1702.05156, Sec. 2.2-2.3 and the appendix's inner update),
+// written branch-free for 64-wide wavefronts:
+//
+//   match tests   hitA = (x-mA)^2 < ts*max(vA, vf); hitC = (x-mC)^2 < ts*max(vC, vf)
+//                 (evaluated as two comparisons, see step())
+//                 (C only counts when A failed: the table index below gives A priority)
+//   update        the matched model (A if hitA, else C) is blended with x using the
+//                 weights of its age (Sec. 2.2): m' = u*m + w*x, V = (m'-x)^2,
+//                 v' = u*v + w*V, age' = min(age+1, age_max)
+//   reset         neither matched: C = (x, var_init, 1).  This is the same update
+//                 with the table slot RESET_SLOT, whose weights are u = 0, w = 1,
+//                 whose variance offset is var_init and whose next age is 1:
+//                 0*m + 1*x = x, (x-x)^2 = 0, 0*v + 1*0 + var_init = var_init, all
+//                 exact in IEEE arithmetic, so no extra select is needed.
+//   exchange      if hitA the result goes to A, else to C
+//   swap          C older than A: A = C, C = (x, var_init, 1) (rare, so a branch
+//                 that the whole wavefront skips when no lane swaps)
+//   mask          background iff (mA-x)^2 <= td*max(mf, ref), ref = vA or x
+//
+// With Acc = double every product and sum is rounded on its own (the library is
+// built with -ffp-contract=off), so results are bit-identical to a scalar FP64
+// evaluation in the paper's order.  With Acc = float the two blends use fused
+// multiply-adds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsgm {
+
+constexpr int RESET_SLOT = 256;  // table slot used by the candidate reset
+constexpr int TABLE_SIZE = 257;  // ages 0..255 plus the reset slot
+
+enum : unsigned { CODE_HIT_A = 1, CODE_HIT_C = 2, CODE_RESET = 4, CODE_SWAP = 8, CODE_FG = 16 };
+
+// Per-age update constants.  `r` is added to the blended variance (0 except in
+// the reset slot); `next` is the age after the update.
+template <typename Acc>
+struct alignas(4 * sizeof(Acc)) TableEntry {
+  Acc u, w, r;
+  int32_t next;
+};
+
+template <typename Acc>
+struct StepConsts {
+  Acc theta_s, theta_d, var_init;
+  Acc ts_vf;  // theta_s * var_floor
+  Acc td_mf;  // theta_d * mask_floor
+  bool printed;  // mask rule: reference is the intensity (true) or var_A (false)
+};
+
+// Fill one table slot.  w = 1/(a+1) (Sec. 2.2) or 1/a (appendix), u = 1 - w,
+// both rounded in the accumulation type; age 0 (never valid) maps to w = 1.
+template <typename Acc>
+__device__ inline TableEntry<Acc> make_entry(int i, int weight_rule, int age_max, Acc var_init) {
+  TableEntry<Acc> e;
+  if (i == RESET_SLOT) {
+    e.u = Acc(0);
+    e.w = Acc(1);
+    e.r = var_init;
+    e.next = 1;
+    return e;
+  }
+  const Acc one = Acc(1);
+  Acc w;
+  if (weight_rule == 1)
+    w = i == 0 ? one : one / Acc(i);
+  else
+    w = one / (Acc(i) + one);
+  e.w = w;
+  e.u = one - w;
+  e.r = Acc(0);
+  e.next = i + 1 < age_max ? i + 1 : age_max;
+  return e;
+}
+
+// blend u*a + w*b
+__device__ __forceinline__ double blend(double u, double a, double w, double b) {
+  return u * a + w * b;  // two roundings and a rounded sum (no contraction)
+}
+__device__ __forceinline__ float blend(float u, float a, float w, float b) {
+  return __builtin_fmaf(u, a, w * b);
+}
+
+template <typename Acc>
+struct Model {
+  Acc mA, vA, mC, vC;
+  int aA, aC;
+};
+
+// One frame of one pixel.  Returns the foreground flag; writes the decision
+// code to *code when CODES.
+template <typename Acc, bool CODES>
+__device__ __forceinline__ bool step(Model<Acc>& s, const Acc x, const StepConsts<Acc>& k,
+                                     const TableEntry<Acc>* __restrict__ tbl, unsigned* code) {
+  // q < theta*max(v, f)  <=>  q < theta*v  or  q < theta*f  for theta >= 0:
+  // rounding is monotone, so round(theta*max(v,f)) = max(round(theta*v),
+  // round(theta*f)); the floor products are per-launch constants.
+  const Acc dA = x - s.mA;
+  const Acc qA = dA * dA;
+  const Acc dC = x - s.mC;
+  const Acc qC = dC * dC;
+  const bool hitA = (qA < k.theta_s * s.vA) | (qA < k.ts_vf);
+  const bool hitC = (qC < k.theta_s * s.vC) | (qC < k.ts_vf);
+
+  const int idx = hitA ? s.aA : (hitC ? s.aC : RESET_SLOT);
+  const Acc m = hitA ? s.mA : s.mC;
+  const Acc v = hitA ? s.vA : s.vC;
+  const TableEntry<Acc> e = tbl[idx];
+
+  const Acc mn = blend(e.u, m, e.w, x);
+  const Acc d = mn - x;
+  const Acc V = d * d;
+  const Acc vn = blend(e.u, v, e.w, V) + e.r;
+  const int an = e.next;
+
+  // the result replaces A if A matched, else C (update or reset)
+  s.mA = hitA ? mn : s.mA;
+  s.vA = hitA ? vn : s.vA;
+  s.aA = hitA ? an : s.aA;
+  s.mC = hitA ? s.mC : mn;
+  s.vC = hitA ? s.vC : vn;
+  s.aC = hitA ? s.aC : an;
+
+  const bool swap = s.aC > s.aA;
+  if (swap) {
+    s.mA = s.mC;
+    s.vA = s.vC;
+    s.aA = s.aC;
+    s.mC = x;
+    s.vC = k.var_init;
+    s.aC = 1;
+  }
+
+  const Acc dd = s.mA - x;
+  const Acc qd = dd * dd;
+  const Acc ref = k.printed ? x : s.vA;
+  const bool fg = !((qd <= k.theta_d * ref) | (qd <= k.td_mf));
+  if (CODES) {
+    *code = (hitA ? CODE_HIT_A : (hitC ? CODE_HIT_C : CODE_RESET)) | (swap ? CODE_SWAP : 0u) |
+            (fg ? CODE_FG : 0u);
+  }
+  return fg;
+}
+
+// ---------------------------------------------------------------- storage types
+struct bf16_t {
+  uint16_t bits;
+};
+
+template <typename In, typename Acc>
+__device__ __forceinline__ Acc to_acc(In v) {
+  return Acc(v);
+}
+template <>
+__device__ __forceinline__ float to_acc<bf16_t, float>(bf16_t v) {
+  return __uint_as_float(uint32_t(v.bits) << 16);
+}
+template <>
+__device__ __forceinline__ double to_acc<bf16_t, double>(bf16_t v) {
+  return double(__uint_as_float(uint32_t(v.bits) << 16));
+}
+
+// P consecutive elements, aligned to their total size so that the compiler
+// emits the widest loads and stores the alignment allows.
+template <typename X, int P>
+struct alignas(sizeof(X) * P) Vec {
+  X v[P];
+};
+
+}  // namespace dsgm

@@ -1,0 +1,64 @@
+"""Helpers shared by the GPU parity tests (not collected by pytest)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+import synth
+from synth import device as sdev
+
+GRID = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}
+ACC_NAME = {torch.float64: "f64", torch.float32: "f32"}
+
+
+def oracle_params(p) -> "oracle.Params":
+    return oracle.Params(theta_s=p.theta_s, theta_d=p.theta_d, var_init=p.var_init,
+                         var_floor=p.var_floor, mask_floor=p.mask_floor, age_max=p.age_max,
+                         weight_rule=p.weight_rule, mask_rule=p.mask_rule)
+
+
+def device_case(seed, T, H, W, in_dtype=torch.float64, acc_dtype=torch.float64, age_max=30):
+    """Frames and a random mid-run state on the device (from the device generator)."""
+    from paper_1702_05156_amd.dsgm import State
+    fr = sdev.frames(seed, T, H, W, in_dtype)
+    st = State(*sdev.state(seed, H, W, acc_dtype, age_max))
+    return fr, st
+
+
+def host_case(seed, T, H, W, in_dtype=torch.float64, acc_dtype=torch.float64, age_max=30,
+              pix=None, t=None):
+    """The same inputs from the host generator, as float64 numpy arrays
+    (frames: (len(t), len(pix))), for the oracle."""
+    x = synth.frames(seed, T, H, W, GRID[in_dtype], t=t, pix=pix)
+    st = synth.state(seed, H, W, ACC_NAME[acc_dtype], age_max, pix=pix)
+    return x, st
+
+
+def state_to_host(st) -> dict:
+    return {"mean_a": st.mean_a.double().cpu().numpy().ravel(),
+            "var_a": st.var_a.double().cpu().numpy().ravel(),
+            "mean_c": st.mean_c.double().cpu().numpy().ravel(),
+            "var_c": st.var_c.double().cpu().numpy().ravel(),
+            "age_a": st.age_a.cpu().numpy().ravel().astype(np.int32),
+            "age_c": st.age_c.cpu().numpy().ravel().astype(np.int32)}
+
+
+def flat(t: torch.Tensor) -> np.ndarray:
+    """(T, H, W) device tensor -> (T, H*W) numpy (float64 for floats)."""
+    a = t.detach()
+    if a.is_floating_point():
+        a = a.double()
+    a = a.cpu().numpy()
+    return a.reshape(a.shape[0], -1)
+
+
+def assert_bit_exact(name, got, want):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    assert got.shape == want.shape, (name, got.shape, want.shape)
+    bad = got != want
+    if np.any(bad):
+        idx = np.argwhere(bad)[:5]
+        raise AssertionError(f"{name}: {int(bad.sum())} of {bad.size} differ; first at "
+                             f"{idx.tolist()}: got {got[bad][:5]} want {want[bad][:5]}")

@@ -1,0 +1,215 @@
+"""GPU forward parity: the HIP path against the FP64 oracle, through the C ABI.
+
+FP64 accumulation is bit-exact by construction (every operation rounded on
+its own in the same order as the oracle), so masks, decision codes, bg and the
+final state must be identical.  FP32/BF16 frames with FP64 accumulation are
+fed to the oracle as the same (exactly upcast) values and must be identical
+too.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from synth import device as sdev
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+
+
+def _run_and_compare(seed, T, H, W, in_dtype=torch.float64, params=None, frames=None):
+    p = params or dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(seed, T, H, W, in_dtype, torch.float64, p.age_max)
+    if frames is not None:
+        fr = frames(fr)
+    x, st0 = G.host_case(seed, T, H, W, in_dtype, torch.float64, p.age_max)
+    out = dsgm.forward(fr, st, p, bg=True, codes=True)
+    torch.cuda.synchronize()
+    ref = oracle.forward(x, st0, G.oracle_params(p))
+    G.assert_bit_exact("codes", G.flat(out["codes"]), ref["codes"])
+    G.assert_bit_exact("masks", G.flat(out["masks"]), ref["masks"])
+    G.assert_bit_exact("bg", G.flat(out["bg"]), ref["bg"])
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k], ref[k])
+    return out, ref
+
+
+def test_generator_twin_bit_identical():
+    T, H, W = 3, 17, 29
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        d = sdev.frames(5, T, H, W, dt)
+        h = synth.frames(5, T, H, W, G.GRID[dt])
+        G.assert_bit_exact(f"frames {dt}", G.flat(d), h)
+    st = sdev.state(6, H, W, torch.float64)
+    hs = synth.state(6, H, W, "f64", 30)
+    for t, k in zip(st, ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c")):
+        G.assert_bit_exact(k, t.double().cpu().numpy().ravel() if k[0] != "a" else
+                           t.cpu().numpy().ravel().astype(np.int32), hs[k])
+    g = sdev.grad_bg(7, T, H, W, torch.float32)
+    G.assert_bit_exact("grad_bg", G.flat(g), synth.grad_bg(7, T, H, W))
+    gs = sdev.grad_state(7, H, W, torch.float64)
+    G.assert_bit_exact("grad_state", gs.cpu().numpy().reshape(4, -1), synth.grad_state(7, H, W))
+
+
+def test_smallest_paper_size_f64_bit_exact():
+    """320x240 frames, 500 of them (the paper's test sequence size), seed 0."""
+    out, ref = _run_and_compare(0, 500, 240, 320)
+    c = ref["codes"]
+    for bit in (oracle.HIT_A, oracle.HIT_C, oracle.RESET, oracle.SWAP, oracle.FG):
+        assert np.any(c & bit)
+
+
+@pytest.mark.parametrize("T,H,W", [(37, 7, 13), (9, 5, 6), (5, 3, 4), (1, 1, 1), (2, 1, 3),
+                                   (13, 64, 257), (6, 2, 4096)])
+def test_ragged_shapes_bit_exact(T, H, W):
+    _run_and_compare(11, T, H, W)
+
+
+@pytest.mark.parametrize("in_dtype", [torch.float32, torch.bfloat16])
+def test_low_precision_frames_f64_state_bit_exact(in_dtype):
+    _run_and_compare(12, 41, 19, 24, in_dtype)
+
+
+@pytest.mark.parametrize("rule,mrule", [(0, 1), (1, 0), (1, 1)])
+def test_other_rules_bit_exact(rule, mrule):
+    p = dsgm.dsgm_params_default(2.0, mrule)
+    p.weight_rule = rule
+    _run_and_compare(13, 60, 16, 40, params=p)
+
+
+def test_age_cap_and_thresholds_bit_exact():
+    p = dsgm.dsgm_params_default(2.0)
+    p.age_max = 3
+    p.theta_s = 5.0
+    p.theta_d = 0.5
+    _run_and_compare(14, 50, 8, 64, params=p)
+    p = dsgm.dsgm_params_default(2.0)
+    p.theta_s = 0.0
+    _run_and_compare(15, 20, 4, 16, params=p)
+
+
+def test_strided_frames_bit_exact():
+    """Frames that are a view into a larger buffer (row and frame padding)."""
+    T, H, W = 23, 9, 20
+
+    def view(fr):
+        big = torch.zeros((T, H + 3, W + 12), dtype=fr.dtype, device=fr.device)
+        big[:, :H, :W] = fr
+        return big[:, :H, :W]
+
+    _run_and_compare(16, T, H, W, frames=view)
+
+
+def test_empty_inputs():
+    p = dsgm.dsgm_params_default(2.0)
+    for T, H, W in ((0, 4, 4), (3, 0, 4), (3, 4, 0)):
+        fr, st = G.device_case(1, max(T, 1), max(H, 1), max(W, 1))
+        fr = torch.zeros((T, H, W), dtype=torch.float64, device="cuda")
+        st = dsgm.State.empty(H, W)
+        dsgm.dsgm_forward(fr, st, p, torch.empty((T, H, W), dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+
+
+def test_launch_shapes_do_not_change_results():
+    T, H, W = 64, 24, 256
+    p = dsgm.dsgm_params_default(2.0)
+    results = []
+    try:
+        for block, vec in ((0, 0), (64, 1), (128, 2), (256, 4), (192, 1)):
+            dsgm.dsgm_set_launch(block, vec)
+            fr, st = G.device_case(17, T, H, W)
+            out = dsgm.forward(fr, st, p, bg=True, codes=True)
+            results.append((out, st))
+    finally:
+        dsgm.dsgm_set_launch(0, 0)
+    torch.cuda.synchronize()
+    o0, s0 = results[0]
+    for o, s in results[1:]:
+        for k in ("masks", "bg", "codes"):
+            assert torch.equal(o[k], o0[k]), k
+        for a, b in zip(s.planes(), s0.planes()):
+            assert torch.equal(a, b)
+
+
+def test_streaming_equals_fused():
+    T, H, W = 30, 12, 40
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(18, T, H, W)
+    st2 = st.clone()
+    fused = dsgm.forward(fr, st, p, bg=True, codes=True)
+    for t in range(T):
+        one = dsgm.forward(fr[t:t + 1], st2, p, bg=True, codes=True)
+        for k in ("masks", "bg", "codes"):
+            assert torch.equal(one[k][0], fused[k][t]), (t, k)
+    for a, b in zip(st.planes(), st2.planes()):
+        assert torch.equal(a, b)
+
+
+def test_checkpoints_hold_the_oracle_state():
+    T, H, W, K = 45, 6, 32, 8
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(19, T, H, W)
+    x, st0 = G.host_case(19, T, H, W)
+    out = dsgm.forward(fr, st, p, ckpt_every=K)
+    torch.cuda.synchronize()
+    ck = out["ckpt"].cpu().numpy()
+    px = H * W
+    fpl = (px * 8 + 255) // 256 * 256
+    apl = (px + 255) // 256 * 256
+    slot = 4 * fpl + 2 * apl
+    cur = st0
+    for j in range((T + K - 1) // K):
+        base = j * slot
+        planes = [ck[base + i * fpl: base + i * fpl + px * 8].view(np.float64) for i in range(4)]
+        ages = [ck[base + 4 * fpl + i * apl: base + 4 * fpl + i * apl + px].astype(np.int32)
+                for i in range(2)]
+        for name, got in zip(("mean_a", "var_a", "mean_c", "var_c"), planes):
+            G.assert_bit_exact(f"ckpt{j}.{name}", got, cur[name])
+        G.assert_bit_exact(f"ckpt{j}.age_a", ages[0], cur["age_a"])
+        G.assert_bit_exact(f"ckpt{j}.age_c", ages[1], cur["age_c"])
+        r = oracle.forward(x[j * K:(j + 1) * K], cur, G.oracle_params(p), bg=False, codes=False)
+        cur = {k: r[k] for k in st0}
+
+
+def test_state_init_from_frame():
+    H, W = 7, 9
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.frames(20, 1, H, W)[0]
+    st = dsgm.State.empty(H, W)
+    dsgm.dsgm_state_init_from_frame(fr, st, p)
+    torch.cuda.synchronize()
+    assert torch.equal(st.mean_a, fr) and torch.equal(st.mean_c, fr)
+    assert torch.all(st.var_a == p.var_init) and torch.all(st.var_c == p.var_init)
+    assert torch.all(st.age_a == 1) and torch.all(st.age_c == 1)
+
+
+@pytest.mark.slow
+def test_full_size_f64_sampled_bit_exact():
+    """1920x2560 pixels x 500 frames, FP64, seed 1, masks only -- the launch
+    configuration the benchmark times.  Pixels are independent, so checking a
+    random sample of pixels against the oracle over all 500 frames is an exact
+    check for those pixels."""
+    T, H, W = 500, 1920, 2560
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(1, T, H, W)
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    dsgm.dsgm_forward(fr, st, p, masks)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    pix = np.unique(np.concatenate([rng.choice(H * W, 4096, replace=False),
+                                    [0, W - 1, H * W - W, H * W - 1]]))
+    x, st0 = G.host_case(1, T, H, W, pix=pix)
+    ref = oracle.forward(x, st0, G.oracle_params(p), bg=False, codes=False)
+    pix_t = torch.as_tensor(pix, device="cuda")
+    got_masks = masks.view(T, H * W)[:, pix_t].cpu().numpy()
+    G.assert_bit_exact("masks", got_masks, ref["masks"])
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k][pix], ref[k])
+    # a property that holds at any size: masks are 0/255 everywhere
+    assert int(((masks != 0) & (masks != 255)).sum()) == 0
+    del fr, masks
