@@ -1,26 +1,38 @@
 #!/usr/bin/env python3
 """Throughput of the DSGM hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs main,mixed,adjoint,batched]
+                    [--no-cpu-baseline]
 
-Workload: the plain method in FP64, one instance of 1920 x 2560 pixels x 500
-frames (64x the paper's 320 x 240 x 500 sequence), frames i.i.d. U[-1,1) and a
-random mid-run model state from seed 1, generated on the device.  One step is
-one call of dsgm_forward over all 500 frames of every pixel (masks out, state
-updated in place; the next step continues from that state, so every step does
-identical work).  Inputs are resident in HBM before the timed region starts.
+Main workload (the `value`): the plain method in FP64, one instance of
+1920 x 2560 pixels x 500 frames (64x the paper's 320 x 240 x 500 sequence),
+frames i.i.d. U[-1,1) and a random mid-run model state from seed 1, generated
+on the device.  One step is one call of dsgm_forward over all 500 frames of
+every pixel (masks out, state updated in place; the next step continues from
+that state, so every step does identical work).  Inputs are resident in HBM
+before the timed region starts.  Element = one pixel-frame update.
 
-Prints one JSON line with the throughput in elements/s (element = one
-pixel-frame update), the roofline of the forward kernel (HBM bound; bytes per
-launch over the kernel's HIP-event duration) and the oracle's CPU throughput on
-a bounded sample.  Parity of this exact launch configuration against the oracle
-is checked by tests/test_gpu_forward.py::test_full_size_f64_sampled_bit_exact.
+Secondary legs, reported under "legs" (same timing method):
+  mixed    BF16 frames (8-bit grid) with FP32 state vs the FP64 path on the same
+           frames: throughput of both, and how far the FP32 results are from the
+           FP64 ones (which the parity tests prove bit-identical to the oracle)
+  adjoint  FP32 frames and state, bg on, checkpoints every 32 frames, upstream
+           gradients ~N(0,1) (seed 2): forward and dsgm_backward throughput
+  batched  512 instances of log-uniform size (seed 3), BF16 frames, FP32 state,
+           one graph-captured persistent launch per step
+
+Prints one JSON line: throughput, the roofline of the main kernel (HBM bound;
+algorithmic bytes per launch over the kernel's HIP-event duration), the
+oracle's CPU throughput on a bounded sample, and the legs.  Parity of each
+timed launch configuration against the oracle is checked by the test suite
+(test_full_size_f64_sampled_bit_exact, test_full_size_f32_forward_and_adjoint_sampled,
+test_full_size_batched_sampled).
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import glob
+import hashlib
 import json
 import os
 import sys
@@ -53,30 +65,203 @@ def load_traffic(kernel: str):
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(T, H, W, seed, target_s=12.0):
+def cpu_baseline(T, H, W, seed, target_s=10.0, chunk_rows=32):
     """The FP64 oracle on a bounded sample of the same workload: whole rows of
-    pixels, all T frames (pixels are independent, so a row sample is the same
-    per-element work)."""
+    pixels over all T frames (pixels are independent, so a row sample is the
+    same per-element work), generated and run in chunks of rows until about
+    `target_s` seconds of oracle time have accumulated or the rows run out.
+    Only the oracle's own time is counted."""
     import numpy as np
     import oracle
     import synth
 
     p = oracle.default_params(2.0)
-
-    def run(rows):
-        pix = np.arange(rows * W)
+    done_rows, n, dt = 0, 0, 0.0
+    while done_rows < H and dt < target_s:
+        rows = min(chunk_rows, H - done_rows)
+        pix = np.arange(done_rows * W, (done_rows + rows) * W)
         x = synth.frames(seed, T, H, W, "f64", pix=pix)
         st = synth.state(seed, H, W, "f64", 30, pix=pix)
         t0 = time.perf_counter()
         oracle.forward(x, st, p, bg=False, codes=False)
-        return time.perf_counter() - t0, rows * W * T
-
-    dt, n = run(4)
-    rows = int(min(H, max(4, 4 * target_s / max(dt, 1e-6))))
-    dt, n = run(rows)
+        dt += time.perf_counter() - t0
+        n += rows * W * T
+        done_rows += rows
+        del x, st
     return {"value": n / dt, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{rows} of {H} rows x {W} columns x {T} frames = {n} elements, "
-                      f"FP64 scalar C, {dt:.1f} s"}
+            "sample": f"rows 0-{done_rows - 1} of {H} x {W} columns x {T} frames = {n} elements "
+                      f"(FP64 scalar C, OpenMP over pixel chunks), {dt:.2f} s of oracle time"}
+
+
+def timed(fn, steps, warmup, stream):
+    """Run fn `warmup` times, then time `steps` calls: (ms per step over the whole
+    region, per-call HIP-event durations in ms), events on `stream`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for i in range(steps):
+        ev[i][0].record(stream)
+        fn()
+        ev[i][1].record(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps, [a.elapsed_time(b) for a, b in ev]
+
+
+def roof(alg_bytes, k_ms):
+    gbs = alg_bytes / (k_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+# ---------------------------------------------------------------- legs
+def leg_mixed(args, dsgm, sdev, torch):
+    """BF16 frames: FP32 state vs FP64 state on the same frames."""
+    T, H, W, seed = 500, 1920, 2560, 1
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.frames(seed, T, H, W, torch.bfloat16)
+    st32 = dsgm.State(*sdev.state(seed, H, W, torch.float32))
+    st64 = dsgm.State(*sdev.state(seed, H, W, torch.float64))
+    m32 = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    m64 = torch.empty_like(m32)
+    stream = torch.cuda.current_stream()
+    s32, s64 = st32.clone(), st64.clone()
+    steps = max(3, args.steps // 2)
+    ms32, k32 = timed(lambda: dsgm.dsgm_forward(fr, s32, p, m32), steps, 2, stream)
+    ms64, k64 = timed(lambda: dsgm.dsgm_forward(fr, s64, p, m64), steps, 2, stream)
+    # accuracy of one pass from the same start, FP32 vs FP64 (the FP64 state
+    # starts from the FP32 state's values, so both see identical inputs)
+    a32 = st32.clone()
+    a64 = dsgm.State(st32.mean_a.double(), st32.var_a.double(), st32.mean_c.double(),
+                     st32.var_c.double(), st32.age_a.clone(), st32.age_c.clone())
+    dsgm.dsgm_forward(fr, a32, p, m32)
+    dsgm.dsgm_forward(fr, a64, p, m64)
+    torch.cuda.synchronize()
+    diff = m32 != m64
+    px_div = int(diff.any(dim=0).sum().item())
+    same = ~diff.any(dim=0)
+    dm = (a32.mean_a.double() - a64.mean_a).abs()
+    dv = (a32.var_a.double() - a64.var_a).abs() / torch.clamp(a64.var_a, min=p.var_init)
+    elems = T * H * W
+    out = {
+        "workload": "bf16 frames 1920x2560x500 seed 1, masks only",
+        "fp32_state": {"elements_per_s": round(elems / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 4),
+                       "roofline": roof(elems * 3 + H * W * 36, float(sum(k32) / len(k32)))},
+        "fp64_state": {"elements_per_s": round(elems / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 4),
+                       "roofline": roof(elems * 3 + H * W * 68, float(sum(k64) / len(k64)))},
+        "speedup_fp32_over_fp64": round(ms64 / ms32, 3),
+        "error_vs_fp64": {
+            "mask_elements_differing_frac": float(diff.sum().item()) / elems,
+            "pixels_with_any_mask_difference_frac": px_div / (H * W),
+            "max_abs_mean_a_err_same_masks": float(dm[same].max().item()) if bool(same.any()) else None,
+            "max_rel_var_a_err_same_masks": float(dv[same].max().item()) if bool(same.any()) else None,
+        },
+    }
+    del fr, st32, st64, m32, m64, s32, s64, a32, a64, diff, same, dm, dv
+    torch.cuda.empty_cache()
+    return out
+
+
+def leg_adjoint(args, dsgm, sdev, torch):
+    T, H, W, K, seed = 500, 1920, 2560, 32, 2
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.frames(seed, T, H, W, torch.float32)
+    st = dsgm.State(*sdev.state(seed, H, W, torch.float32))
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    bg = torch.empty((T, H, W), dtype=torch.float32, device="cuda")
+    ck = torch.empty(dsgm.dsgm_ckpt_bytes(T, H, W, dsgm.ACC_F32, K), dtype=torch.uint8, device="cuda")
+    gbg = sdev.grad_bg(seed + 100, T, H, W, torch.float32)
+    gst = sdev.grad_state(seed + 100, H, W, torch.float32)
+    gst = tuple(gst[i].contiguous() for i in range(4))
+    gx = torch.empty((T, H, W), dtype=torch.float32, device="cuda")
+    gs0 = tuple(torch.empty((H, W), dtype=torch.float32, device="cuda") for _ in range(4))
+    gvi = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(dsgm.dsgm_workspace_bytes(T, H, W, dsgm.ACC_F32), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    st0 = st.clone()
+    steps = max(3, args.steps // 2)
+    msf, kf = timed(lambda: dsgm.dsgm_forward(fr, st, p, masks, bg, ck, K), steps, 2, stream)
+    # the backward of one forward pass from the initial state
+    for a, b in zip(st.planes(), st0.planes()):
+        a.copy_(b)
+    dsgm.dsgm_forward(fr, st, p, masks, bg, ck, K)
+    msb, kb = timed(lambda: dsgm.dsgm_backward(fr, p, ck, K, dsgm.ACC_F32, gbg, gst, gx, gs0, gvi, ws),
+                    steps, 1, stream)
+    elems, px = T * H * W, H * W
+    ck_slots = (T + K - 1) // K
+    fwd_bytes = elems * (4 + 1 + 4) + px * 36
+    bwd_bytes = elems * 12 + px * (16 + 16 + 8)
+    out = {
+        "workload": "fp32 frames and state 1920x2560x500 seed 2, bg on, K=32",
+        "forward": {"elements_per_s": round(elems / (msf * 1e-3), 1), "ms_per_step": round(msf, 4),
+                    "roofline": roof(fwd_bytes, float(sum(kf) / len(kf))),
+                    "checkpoint_bytes_written": ck_slots * px * 18},
+        "backward": {"elements_per_s": round(elems / (msb * 1e-3), 1), "ms_per_step": round(msb, 4),
+                     "roofline": roof(bwd_bytes, float(sum(kb) / len(kb))),
+                     "checkpoint_bytes_read": ck_slots * px * 18},
+        "grad_var_init": float(gvi.item()),
+    }
+    del fr, st, st0, masks, bg, ck, gbg, gst, gx, gs0, gvi, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_shapes(seed=3, n=512):
+    """Instance sizes: m = 256^u with u ~ U[0,1) (synth stream 10), width
+    8*round(40 m^(1/4)), height 8*round(30 m^(1/4)), frames round(32 m^(1/2)):
+    elements ~ m * (320*240*32), log-uniform over 1x..256x of that unit."""
+    import numpy as np
+    import synth
+    u = (synth.uniform(seed, 10, np.arange(n), "f64") + 1.0) / 2.0
+    m = 256.0 ** u
+    W = 8 * np.round(40 * m ** 0.25).astype(int)
+    H = 8 * np.round(30 * m ** 0.25).astype(int)
+    T = np.round(32 * m ** 0.5).astype(int)
+    return [(int(t), int(h), int(w)) for t, h, w in zip(T, H, W)]
+
+
+def batch_seed(i: int) -> int:
+    return 3000 + i
+
+
+def leg_batched(args, dsgm, sdev, torch):
+    shapes = batch_shapes()
+    p = dsgm.dsgm_params_default(2.0)
+    items = []
+    for i, (T, H, W) in enumerate(shapes):
+        fr = sdev.frames(batch_seed(i), T, H, W, torch.bfloat16)
+        st = dsgm.State(*sdev.state(batch_seed(i), H, W, torch.float32))
+        items.append((fr, st, torch.empty((T, H, W), dtype=torch.uint8, device="cuda"), None))
+    batch = dsgm.Batch(items)
+    stream = torch.cuda.current_stream()
+    batch.run(p)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    with torch.cuda.graph(g, stream=s):
+        batch.run(p)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 4)
+    ms, kk = timed(g.replay, steps, 1, stream)
+    elems = batch.plan.total_elements
+    px = sum(H * W for _, H, W in shapes)
+    alg = elems * 3 + px * 36
+    out = {"workload": "512 instances, log-uniform 1x..256x of 320x240x32, bf16 frames, fp32 state, "
+                       "masks only, seed 3",
+           "instances": len(shapes), "total_elements": int(elems), "work_items": int(batch.plan.n_items),
+           "persistent_workgroups": int(batch.plan.grid),
+           "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+           "roofline": roof(alg, float(sum(kk) / len(kk)))}
+    del items, batch, g
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -84,6 +269,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--legs", default="main,mixed,adjoint,batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
@@ -112,51 +298,40 @@ def main():
     from paper_1702_05156_amd import dsgm
     from synth import device as sdev
 
+    legs = set(args.legs.split(","))
     T, H, W, seed = 500, 1920, 2560, 1
     p = dsgm.dsgm_params_default(2.0)
     fr = sdev.frames(seed, T, H, W, torch.float64)
     st = dsgm.State(*sdev.state(seed, H, W, torch.float64))
     masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        dsgm.dsgm_forward(fr, st, p, masks)
-    torch.cuda.synchronize()
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_wall = time.perf_counter()
-    start.record(stream)
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        dsgm.dsgm_forward(fr, st, p, masks)
-        ev[i][1].record(stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
+    ms_step, kern_ms = timed(lambda: dsgm.dsgm_forward(fr, st, p, masks), args.steps, args.warmup,
+                             stream)
     t_wall = time.perf_counter() - t_wall
-    total_ms = start.elapsed_time(stop)
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
-    ms_step = total_ms / args.steps
     elems = T * H * W
     value = elems / (ms_step * 1e-3)
-
     px = H * W
     alg_bytes = elems * (8 + 1) + px * (4 * 8 + 2) * 2
     k_avg = float(np.mean(kern_ms))
-    achieved = alg_bytes / (k_avg * 1e-3) / 1e9
     kernel = "fwd_kernel_f64_f64_p4"
-    traffic = load_traffic(kernel)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kernel, "kernel_ms_avg": round(k_avg, 4),
-            "alg_bytes_per_launch": alg_bytes, "alg_bytes_per_element": round(alg_bytes / elems, 4)}
+    rf = roof(alg_bytes, k_avg)
+    rf.update({"traffic": load_traffic(kernel), "kernel": kernel, "kernel_ms_avg": round(k_avg, 4),
+               "alg_bytes_per_launch": alg_bytes,
+               "alg_bytes_per_element": round(alg_bytes / elems, 4)})
+    del fr, st, masks
+    torch.cuda.empty_cache()
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(T, H, W, seed)
+    out_legs = {}
+    if "mixed" in legs:
+        out_legs["mixed"] = leg_mixed(args, dsgm, sdev, torch)
+    if "adjoint" in legs:
+        out_legs["adjoint"] = leg_adjoint(args, dsgm, sdev, torch)
+    if "batched" in legs:
+        out_legs["batched"] = leg_batched(args, dsgm, sdev, torch)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(T, H, W, seed)
 
     out = {
         "metric": "hot-path elements/s and % roofline (fwd+adjoint), mixed vs FP64 at tol",
@@ -166,7 +341,7 @@ def main():
         "config": {"workload": "dsgm_forward_fp64_1920x2560x500", "T": T, "H": H, "W": W,
                    "frames": "f64", "state": "f64", "outputs": "masks", "seed": seed,
                    "element": "one pixel-frame update"},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": rf, "cpu_baseline": cpu, "legs": out_legs,
         "wall_s_timed": round(t_wall, 3),
     }
     print(json.dumps(out), flush=True)

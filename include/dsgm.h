@@ -154,6 +154,94 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
 /* bytes of the checkpoint buffer for dsgm_forward/dsgm_backward (0 on bad args) */
 size_t dsgm_ckpt_bytes(dsgm_shape shape, dsgm_acc acc, int32_t ckpt_every);
 
+/* bytes of the workspace dsgm_backward needs: H*W doubles (per-pixel
+ * contributions to d/d(var_init), padded to 256 B) plus 4 KiB of partial sums
+ * (0 on bad arguments) */
+size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc);
+
+/*
+ * Reverse-mode derivative of the differentiable outputs -- bg after every frame
+ * and the final mean_a, var_a, mean_c, var_c -- with respect to the frames,
+ * the initial four float planes and var_init, with every decision (match,
+ * reset, swap) held at the value the forward pass took.  The paper has no
+ * derivative; this is the chain rule through the Sec. 2.2 update and the
+ * Sec. 2.3 reset and swap (the foreground mask has no derivative).  Segments of
+ * ckpt_every frames are recomputed from `ckpt`, which dsgm_forward wrote with
+ * the same frames, params, shape and ckpt_every, and swept backwards.
+ *   frames         as given to dsgm_forward
+ *   ckpt           dsgm_ckpt_bytes(shape, acc, ckpt_every) bytes (device)
+ *   grad_bg        T x H x W, accumulation type, strided like the frames (NULL = zero)
+ *   grad_state_T   upstream gradient of the final planes (host struct or NULL = zero)
+ *   grad_frames    T x H x W, accumulation type, strided like the frames (out)
+ *   grad_state0    gradient of the initial planes (host struct of device planes, out)
+ *   grad_var_init  one double on the device (out): the H*W per-pixel terms are
+ *                  accumulated in FP64 and added in a fixed order with
+ *                  compensated (error-free two-sum) arithmetic, so it is
+ *                  reproducible and independent of the launch shape
+ *   workspace      dsgm_workspace_bytes(shape, acc) bytes of device memory;
+ *                  smaller returns DSGM_E_WORKSPACE
+ * With ACC_F64, grad_frames and grad_state0 are bit-identical to a scalar FP64
+ * evaluation of the same chain rule in the same order.
+ */
+int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
+                  const dsgm_params* params /* host */, const void* ckpt, int32_t ckpt_every,
+                  const void* grad_bg, const dsgm_grad_state* grad_state_T /* host, or NULL */,
+                  void* grad_frames, dsgm_grad_state* grad_state0 /* host */,
+                  double* grad_var_init, void* workspace, size_t workspace_bytes,
+                  hipStream_t stream);
+
+/* one instance of a batch: its own sizes, strides, frames, state and outputs */
+typedef struct {
+  dsgm_shape shape;
+  const void* frames;
+  dsgm_state state;
+  uint8_t* masks;
+  void* bg; /* NULL: no bg output */
+} dsgm_instance;
+
+/* host-side handle of a planned batch (plain data, owned by the caller) */
+typedef struct {
+  void* device_plan;      /* the caller's plan buffer (device)                 */
+  int64_t n_items;        /* work items: (instance, up to 64 pixel groups)     */
+  int64_t total_elements; /* sum over instances of T*H*W                      */
+  int32_t n_instances;
+  int32_t in_dtype, acc;
+  int32_t vector;         /* pixels per lane, common to all instances         */
+  int32_t grid;           /* persistent workgroups (device-resident count)    */
+  int32_t has_bg;
+} dsgm_batch_plan;
+
+/* bytes of the device plan buffer for these instances (0 on bad arguments) */
+size_t dsgm_batch_plan_bytes(const dsgm_instance* instances /* host */, int32_t n,
+                             dsgm_in_dtype in_dtype, dsgm_acc acc);
+
+/*
+ * Plan many independent instances (different sizes, frame counts, strides) for
+ * one persistent launch.  Each instance is cut into work items of up to 64
+ * pixel groups (one wavefront's work over all of the instance's frames); the
+ * items are ordered longest-first (frames x groups, LPT) and written, with the
+ * instance descriptors, to `plan_buffer` (device, 256-byte aligned,
+ * dsgm_batch_plan_bytes bytes, owned by the caller, which keeps it and every
+ * instance buffer alive while the plan is used).  The pixels-per-lane width is
+ * the widest every instance allows.  This call copies the plan to the device
+ * and synchronizes `stream`; it is not meant for the hot loop.
+ */
+int dsgm_plan_batched(const dsgm_instance* instances /* host */, int32_t n, dsgm_in_dtype in_dtype,
+                      dsgm_acc acc, void* plan_buffer, size_t plan_bytes,
+                      dsgm_batch_plan* plan /* host, out */, hipStream_t stream);
+
+/*
+ * Run every instance of a plan through all of its frames (the per-instance
+ * results are those of dsgm_forward on that instance alone): one small kernel
+ * resets the plan's work counter, then one persistent kernel whose wavefronts
+ * take items from it until none are left.  Enqueues exactly these two kernels
+ * and nothing else (no allocation, no copy, no synchronization), so the call
+ * can be captured into a HIP graph and replayed.  Launches of one plan must
+ * not overlap (they share the counter).
+ */
+int dsgm_forward_batched(const dsgm_batch_plan* plan /* host */, const dsgm_params* params /* host */,
+                         hipStream_t stream);
+
 /* human-readable name of a status code (static string) */
 const char* dsgm_status_string(int status);
 

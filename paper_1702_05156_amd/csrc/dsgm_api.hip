@@ -5,7 +5,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "dsgm.h"
 #include "dsgm_internal.h"
@@ -101,6 +103,62 @@ int pick_vector(const dsgm_shape& s, const void* const* ptrs, const size_t* elem
 
 int g_block_override = 0;  // set by dsgm_set_launch (tuning)
 int g_vector_override = 0;
+
+// ---------------------------------------------------------------- batching
+constexpr int64_t kPlanHeader = 256;  // the item counter lives here
+
+int64_t pad_to(int64_t b, int64_t a) { return (b + a - 1) / a * a; }
+
+struct PlanLayout {
+  int P = 4;
+  int64_t n_items = 0, total = 0, inst_off = 0, items_off = 0, bytes = 0;
+  bool bg = false;
+};
+
+// validate the instances and lay out the device plan; no HIP call
+int plan_layout(const dsgm_instance* inst, int32_t n, int in_dtype, int acc, PlanLayout* L) {
+  int rc;
+  if ((rc = check_types(in_dtype, acc))) return rc;
+  if (n < 0 || (n > 0 && !inst)) return fail(DSGM_E_ARG, "instances: NULL or negative count");
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc);
+  int P = 4;
+  L->bg = false;
+  for (int32_t i = 0; i < n; ++i) {
+    const dsgm_instance& I = inst[i];
+    if ((rc = check_shape(I.shape, ie > ae ? ie : ae)))
+      return fail(rc, "instance %d: %s", i, g_last_error);
+    const int64_t px = I.shape.H * I.shape.W;
+    if (px == 0 || I.shape.T == 0) continue;
+    if (!I.frames || !I.masks || !I.state.mean_a || !I.state.var_a || !I.state.mean_c ||
+        !I.state.var_c || !I.state.age_a || !I.state.age_c)
+      return fail(DSGM_E_ARG, "instance %d: a required pointer is NULL", i);
+    const void* ptrs[10] = {I.frames, I.masks, I.bg, I.state.mean_a, I.state.var_a,
+                            I.state.mean_c, I.state.var_c, I.state.age_a, I.state.age_c,
+                            nullptr};
+    const size_t elem[10] = {ie, 1, ae, ae, ae, ae, ae, 1, 1, 1};
+    for (int k = 0; k < 9; ++k)
+      if (ptrs[k] && !aligned(ptrs[k], elem[k]))
+        return fail(DSGM_E_ALIGN, "instance %d: pointer %d not aligned to %zu bytes", i, k, elem[k]);
+    P = std::min(P, pick_vector(I.shape, ptrs, elem, 9));
+    if (I.bg) L->bg = true;
+  }
+  if (g_vector_override && P % g_vector_override == 0) P = g_vector_override;
+  int64_t items = 0, total = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const dsgm_shape& s = inst[i].shape;
+    if (s.H * s.W == 0 || s.T == 0) continue;
+    items += (s.H * (s.W / P) + 63) / 64;
+    total += s.T * s.H * s.W;
+  }
+  L->P = P;
+  L->n_items = items;
+  L->total = total;
+  L->inst_off = kPlanHeader;
+  L->items_off = kPlanHeader + pad_to(int64_t(n) * int64_t(sizeof(dsgm::BatchInst)), 256);
+  L->bytes = L->items_off + pad_to(items * int64_t(sizeof(dsgm::BatchItem)), 256);
+  return DSGM_OK;
+}
+
 
 }  // namespace
 
@@ -255,6 +313,212 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   const int block = g_block_override ? g_block_override : 256;
   hipError_t e = dsgm::launch_forward(a, in_dtype, acc, P, block, stream);
   if (e != hipSuccess) return hip_fail(e, "dsgm_forward launch");
+  return ok();
+}
+
+size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc) {
+  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32) return 0;
+  if (shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;
+  return size_t(pad256(shape.H * shape.W * 8)) + dsgm::reduce_workspace_bytes();
+}
+
+int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
+                  const dsgm_params* params, const void* ckpt, int32_t ckpt_every,
+                  const void* grad_bg, const dsgm_grad_state* grad_state_T, void* grad_frames,
+                  dsgm_grad_state* grad_state0, double* grad_var_init, void* workspace,
+                  size_t workspace_bytes, hipStream_t stream) {
+  int rc;
+  if ((rc = check_types(in_dtype, acc))) return rc;
+  if ((rc = check_params(params))) return rc;
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc);
+  if ((rc = check_shape(shape, ie > ae ? ie : ae))) return rc;
+  const int64_t px = shape.H * shape.W;
+  const int64_t n = shape.T * px;
+  if (!grad_var_init) return fail(DSGM_E_ARG, "grad_var_init is NULL");
+  if (!workspace) return fail(DSGM_E_ARG, "workspace is NULL");
+  const size_t need = dsgm_workspace_bytes(shape, acc);
+  if (workspace_bytes < need)
+    return fail(DSGM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
+  if (px > 0) {
+    if (!grad_state0 || !grad_state0->mean_a || !grad_state0->var_a || !grad_state0->mean_c ||
+        !grad_state0->var_c)
+      return fail(DSGM_E_ARG, "grad_state0 or one of its planes is NULL");
+    if (grad_state_T && (!grad_state_T->mean_a || !grad_state_T->var_a ||
+                         !grad_state_T->mean_c || !grad_state_T->var_c))
+      return fail(DSGM_E_ARG, "a plane of grad_state_T is NULL");
+  }
+  if (n > 0) {
+    if (!frames) return fail(DSGM_E_ARG, "frames is NULL");
+    if (!grad_frames) return fail(DSGM_E_ARG, "grad_frames is NULL");
+    if (!ckpt) return fail(DSGM_E_ARG, "ckpt is NULL");
+    if (ckpt_every < 1) return fail(DSGM_E_ARG, "ckpt_every = %d < 1", ckpt_every);
+  }
+  const void* ptrs[14] = {frames, grad_bg, grad_frames, workspace, grad_var_init, ckpt,
+                          grad_state0 ? grad_state0->mean_a : nullptr,
+                          grad_state0 ? grad_state0->var_a : nullptr,
+                          grad_state0 ? grad_state0->mean_c : nullptr,
+                          grad_state0 ? grad_state0->var_c : nullptr,
+                          grad_state_T ? grad_state_T->mean_a : nullptr,
+                          grad_state_T ? grad_state_T->var_a : nullptr,
+                          grad_state_T ? grad_state_T->mean_c : nullptr,
+                          grad_state_T ? grad_state_T->var_c : nullptr};
+  const size_t elem[14] = {ie, ae, ae, 8, 8, 16, ae, ae, ae, ae, ae, ae, ae, ae};
+  for (int i = 0; i < 14; ++i)
+    if (ptrs[i] && !aligned(ptrs[i], elem[i]))
+      return fail(DSGM_E_ALIGN, "pointer argument %d is not aligned to %zu bytes", i, elem[i]);
+
+  double* gvi_px = static_cast<double*>(workspace);
+  double* partial = reinterpret_cast<double*>(static_cast<char*>(workspace) + pad256(px * 8));
+  hipError_t e;
+  if (px > 0) {
+    dsgm::BwdArgs a;
+    memset(&a, 0, sizeof(a));
+    a.frames = frames;
+    a.ckpt = ckpt;
+    a.grad_bg = grad_bg;
+    if (grad_state_T) {
+      a.gst_mean_a = grad_state_T->mean_a;
+      a.gst_var_a = grad_state_T->var_a;
+      a.gst_mean_c = grad_state_T->mean_c;
+      a.gst_var_c = grad_state_T->var_c;
+    }
+    a.grad_frames = grad_frames;
+    a.gs0_mean_a = grad_state0->mean_a;
+    a.gs0_var_a = grad_state0->var_a;
+    a.gs0_mean_c = grad_state0->mean_c;
+    a.gs0_var_c = grad_state0->var_c;
+    a.gvi_px = gvi_px;
+    a.ckpt_every = ckpt_every >= 1 ? ckpt_every : 1;
+    a.ckpt_fplane = pad256(px * int64_t(ae));
+    a.ckpt_aplane = pad256(px);
+    a.ckpt_slot_bytes = 4 * a.ckpt_fplane + 2 * a.ckpt_aplane;
+    a.T = shape.T;
+    a.H = shape.H;
+    a.W = shape.W;
+    a.row_stride = shape.row_stride;
+    a.frame_stride = shape.frame_stride;
+    a.theta_s = params->theta_s;
+    a.theta_d = params->theta_d;
+    a.var_init = params->var_init;
+    a.var_floor = params->var_floor;
+    a.mask_floor = params->mask_floor;
+    a.age_max = params->age_max;
+    a.weight_rule = params->weight_rule;
+    a.mask_rule = params->mask_rule;
+    e = dsgm::launch_backward(a, in_dtype, acc, stream);
+    if (e != hipSuccess) return hip_fail(e, "dsgm_backward launch");
+  }
+  e = dsgm::launch_reduce(gvi_px, px, partial, grad_var_init, stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_backward reduction launch");
+  return ok();
+}
+
+size_t dsgm_batch_plan_bytes(const dsgm_instance* instances, int32_t n, dsgm_in_dtype in_dtype,
+                             dsgm_acc acc) {
+  PlanLayout L;
+  if (plan_layout(instances, n, in_dtype, acc, &L)) return 0;
+  return size_t(L.bytes);
+}
+
+int dsgm_plan_batched(const dsgm_instance* instances, int32_t n, dsgm_in_dtype in_dtype,
+                      dsgm_acc acc, void* plan_buffer, size_t plan_bytes, dsgm_batch_plan* plan,
+                      hipStream_t stream) {
+  PlanLayout L;
+  int rc = plan_layout(instances, n, in_dtype, acc, &L);
+  if (rc) return rc;
+  if (!plan) return fail(DSGM_E_ARG, "plan is NULL");
+  if (!plan_buffer) return fail(DSGM_E_ARG, "plan_buffer is NULL");
+  if (!aligned(plan_buffer, 256)) return fail(DSGM_E_ALIGN, "plan_buffer is not 256-byte aligned");
+  if (plan_bytes < size_t(L.bytes))
+    return fail(DSGM_E_WORKSPACE, "plan buffer of %zu bytes, %lld needed", plan_bytes,
+                (long long)L.bytes);
+  const int P = L.P;
+  std::vector<char> host(size_t(L.bytes), 0);
+  auto* desc = reinterpret_cast<dsgm::BatchInst*>(host.data() + L.inst_off);
+  auto* items = reinterpret_cast<dsgm::BatchItem*>(host.data() + L.items_off);
+  int64_t k = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const dsgm_instance& I = instances[i];
+    dsgm::BatchInst& d = desc[i];
+    d.frames = I.frames;
+    d.masks = I.masks;
+    d.bg = I.bg;
+    d.state[0] = I.state.mean_a;
+    d.state[1] = I.state.var_a;
+    d.state[2] = I.state.mean_c;
+    d.state[3] = I.state.var_c;
+    d.state[4] = I.state.age_a;
+    d.state[5] = I.state.age_c;
+    d.T = I.shape.T;
+    d.H = I.shape.H;
+    d.W = I.shape.W;
+    d.row_stride = I.shape.row_stride;
+    d.frame_stride = I.shape.frame_stride;
+    d.groups_per_row = I.shape.W / P;
+    if (I.shape.H * I.shape.W == 0 || I.shape.T == 0) continue;
+    const int64_t ng = I.shape.H * (I.shape.W / P);
+    for (int64_t g = 0; g < ng; g += 64) {
+      items[k].inst = i;
+      items[k].first_group = int32_t(g);
+      items[k].count = int32_t(std::min<int64_t>(64, ng - g));
+      items[k].pad = 0;
+      ++k;
+    }
+  }
+  // longest processing time first: cost = frames x groups; ties keep instance order
+  std::stable_sort(items, items + k, [&](const dsgm::BatchItem& x, const dsgm::BatchItem& y) {
+    return desc[x.inst].T * x.count > desc[y.inst].T * y.count;
+  });
+  // persistent grid: as many 256-thread blocks as fit on the device at once
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const void* fn = dsgm::batched_kernel_symbol(in_dtype, acc, P, L.bg);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_plan_batched: device query");
+  e = hipMemcpyAsync(plan_buffer, host.data(), size_t(L.bytes), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_plan_batched: copy");
+  plan->device_plan = plan_buffer;
+  plan->n_items = L.n_items;
+  plan->total_elements = L.total;
+  plan->n_instances = n;
+  plan->in_dtype = in_dtype;
+  plan->acc = acc;
+  plan->vector = P;
+  plan->grid = std::max(1, per_cu) * std::max(1, ncu);
+  plan->has_bg = L.bg ? 1 : 0;
+  return ok();
+}
+
+int dsgm_forward_batched(const dsgm_batch_plan* plan, const dsgm_params* params,
+                         hipStream_t stream) {
+  int rc;
+  if (!plan || !plan->device_plan) return fail(DSGM_E_ARG, "plan is NULL or not planned");
+  if ((rc = check_types(plan->in_dtype, plan->acc))) return rc;
+  if ((rc = check_params(params))) return rc;
+  if (plan->vector != 1 && plan->vector != 2 && plan->vector != 4)
+    return fail(DSGM_E_ARG, "plan.vector = %d invalid", plan->vector);
+  if (plan->n_items == 0) return ok();
+  char* base = static_cast<char*>(plan->device_plan);
+  dsgm::BatchArgs a;
+  memset(&a, 0, sizeof(a));
+  a.counter = reinterpret_cast<unsigned long long*>(base);
+  a.inst = reinterpret_cast<const dsgm::BatchInst*>(base + kPlanHeader);
+  a.items = reinterpret_cast<const dsgm::BatchItem*>(
+      base + kPlanHeader + pad_to(int64_t(plan->n_instances) * int64_t(sizeof(dsgm::BatchInst)), 256));
+  a.n_items = plan->n_items;
+  a.theta_s = params->theta_s;
+  a.theta_d = params->theta_d;
+  a.var_init = params->var_init;
+  a.var_floor = params->var_floor;
+  a.mask_floor = params->mask_floor;
+  a.age_max = params->age_max;
+  a.weight_rule = params->weight_rule;
+  a.mask_rule = params->mask_rule;
+  hipError_t e = dsgm::launch_batched(a, plan->in_dtype, plan->acc, plan->vector,
+                                      plan->has_bg != 0, plan->grid, stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_forward_batched launch");
   return ok();
 }
 

@@ -91,11 +91,21 @@ struct Model {
   int aA, aC;
 };
 
-// One frame of one pixel.  Returns the foreground flag; writes the decision
-// code to *code when CODES.
-template <typename Acc, bool CODES>
-__device__ __forceinline__ bool step(Model<Acc>& s, const Acc x, const StepConsts<Acc>& k,
-                                     const TableEntry<Acc>* __restrict__ tbl, unsigned* code) {
+// What one step decided, for the reverse sweep: the table slot used (the
+// matched model's age, or RESET_SLOT), whether A matched, whether C was promoted,
+// and d = (updated mean) - x of the blend.
+template <typename Acc>
+struct StepRecord {
+  Acc d;
+  int idx;
+  bool hitA, hitC, swap, fg;
+};
+
+// One frame of one pixel (state updated in place).
+template <typename Acc>
+__device__ __forceinline__ StepRecord<Acc> step_rec(Model<Acc>& s, const Acc x,
+                                                    const StepConsts<Acc>& k,
+                                                    const TableEntry<Acc>* __restrict__ tbl) {
   // q < theta*max(v, f)  <=>  q < theta*v  or  q < theta*f  for theta >= 0:
   // rounding is monotone, so round(theta*max(v,f)) = max(round(theta*v),
   // round(theta*f)); the floor products are per-launch constants.
@@ -139,11 +149,72 @@ __device__ __forceinline__ bool step(Model<Acc>& s, const Acc x, const StepConst
   const Acc qd = dd * dd;
   const Acc ref = k.printed ? x : s.vA;
   const bool fg = !((qd <= k.theta_d * ref) | (qd <= k.td_mf));
+  StepRecord<Acc> r;
+  r.d = d;
+  r.idx = idx;
+  r.hitA = hitA;
+  r.hitC = hitC && !hitA;
+  r.swap = swap;
+  r.fg = fg;
+  return r;
+}
+
+// One frame of one pixel.  Returns the foreground flag; writes the decision
+// code to *code when CODES.
+template <typename Acc, bool CODES>
+__device__ __forceinline__ bool step(Model<Acc>& s, const Acc x, const StepConsts<Acc>& k,
+                                     const TableEntry<Acc>* __restrict__ tbl, unsigned* code) {
+  const StepRecord<Acc> r = step_rec<Acc>(s, x, k, tbl);
   if (CODES) {
-    *code = (hitA ? CODE_HIT_A : (hitC ? CODE_HIT_C : CODE_RESET)) | (swap ? CODE_SWAP : 0u) |
-            (fg ? CODE_FG : 0u);
+    *code = (r.hitA ? CODE_HIT_A : (r.hitC ? CODE_HIT_C : CODE_RESET)) |
+            (r.swap ? CODE_SWAP : 0u) | (r.fg ? CODE_FG : 0u);
   }
-  return fg;
+  return r.fg;
+}
+
+// Adjoint of one step, decisions fixed (the chain rule through step_rec):
+//   bg = mA after the step           gmA += gbg
+//   swap: A <- C, C <- (x, var_init) gx += gmC, gvi += gvC, (gmC, gvC) <- (gmA, gvA), A's = 0
+//   blend of the matched model M (with the reset as the slot u = 0, w = 1, d = 0):
+//     gV = w*gv, gd = 2*d*gV, gmn = gm + gd, gx += w*gmn - gd, gv <- u*gv, gm <- u*gmn
+//   reset slot: var_init enters the new variance with slope 1: gvi += gv
+// The operation order is that of a scalar FP64 evaluation, so with Acc = double
+// the per-element results are bit-identical to it.
+template <typename Acc>
+struct Adjoint {
+  Acc gmA, gvA, gmC, gvC;
+  double gvi;  // this pixel's contribution to d/d(var_init), in FP64
+};
+
+template <typename Acc, bool HAS_GBG>
+__device__ __forceinline__ Acc reverse_step(Adjoint<Acc>& g, const Acc gbg, const Acc d,
+                                            const int idx, const bool hitA, const bool swap,
+                                            const TableEntry<Acc>* __restrict__ tbl) {
+  if (HAS_GBG) g.gmA = g.gmA + gbg;
+  Acc gx = Acc(0);
+  if (swap) {
+    gx = gx + g.gmC;
+    g.gvi += double(g.gvC);
+    g.gmC = g.gmA;
+    g.gvC = g.gvA;
+    g.gmA = Acc(0);
+    g.gvA = Acc(0);
+  }
+  const TableEntry<Acc> e = tbl[idx];
+  const Acc gm = hitA ? g.gmA : g.gmC;
+  const Acc gv = hitA ? g.gvA : g.gvC;
+  const Acc gV = e.w * gv;
+  const Acc gd = (Acc(2) * d) * gV;
+  const Acc gmn = gm + gd;
+  gx = gx + (e.w * gmn - gd);
+  const Acc gvn = e.u * gv;
+  const Acc gmo = e.u * gmn;
+  if (idx == RESET_SLOT) g.gvi += double(gv);
+  g.gmA = hitA ? gmo : g.gmA;
+  g.gvA = hitA ? gvn : g.gvA;
+  g.gmC = hitA ? g.gmC : gmo;
+  g.gvC = hitA ? g.gvC : gvn;
+  return gx;
 }
 
 // ---------------------------------------------------------------- storage types

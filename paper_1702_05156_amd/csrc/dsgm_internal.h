@@ -33,6 +33,68 @@ struct FwdArgs {
   int32_t age_max, weight_rule, mask_rule;
 };
 
+// Arguments of the backward kernels.
+struct BwdArgs {
+  const void* frames;
+  const void* ckpt;
+  const void* grad_bg;     // NULL: zero
+  const void* gst_mean_a;  // upstream gradient of the final planes (all NULL: zero)
+  const void* gst_var_a;
+  const void* gst_mean_c;
+  const void* gst_var_c;
+  void* grad_frames;
+  void* gs0_mean_a;
+  void* gs0_var_a;
+  void* gs0_mean_c;
+  void* gs0_var_c;
+  double* gvi_px;          // H*W per-pixel contributions (workspace)
+  int64_t ckpt_every, ckpt_slot_bytes, ckpt_fplane, ckpt_aplane;
+  int64_t T, H, W, row_stride, frame_stride;
+  double theta_s, theta_d, var_init, var_floor, mask_floor;
+  int32_t age_max, weight_rule, mask_rule;
+};
+
+hipError_t launch_backward(const BwdArgs& a, int in_dtype, int acc, hipStream_t stream);
+
+// deterministic compensated sum of n doubles into out[0]; partial holds
+// reduce_workspace_bytes() bytes
+size_t reduce_workspace_bytes();
+hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* out,
+                         hipStream_t stream);
+
+// Batched forward: device-side descriptors written by the host planner.
+struct BatchInst {
+  const void* frames;
+  uint8_t* masks;
+  void* bg;  // NULL: no bg for this instance
+  void* state[6];
+  int64_t T, H, W, row_stride, frame_stride, groups_per_row;
+};
+
+// one wavefront's work: `count` (<= 64) consecutive pixel groups of one instance
+struct BatchItem {
+  int32_t inst;
+  int32_t first_group;
+  int32_t count;
+  int32_t pad;
+};
+
+static_assert(sizeof(BatchInst) == 120, "plan layout: instance descriptor size");
+static_assert(sizeof(BatchItem) == 16, "plan layout: item size");
+
+struct BatchArgs {
+  unsigned long long* counter;  // next item; reset to 0 by each launch
+  const BatchInst* inst;
+  const BatchItem* items;
+  int64_t n_items;
+  double theta_s, theta_d, var_init, var_floor, mask_floor;
+  int32_t age_max, weight_rule, mask_rule;
+};
+
+const void* batched_kernel_symbol(int in_dtype, int acc, int P, bool bg);
+hipError_t launch_batched(const BatchArgs& a, int in_dtype, int acc, int P, bool bg, int grid,
+                          hipStream_t stream);
+
 // in_dtype: 0 f64, 1 f32, 2 bf16; acc: 0 f64, 1 f32; P in {1, 2, 4}
 hipError_t launch_forward(const FwdArgs& a, int in_dtype, int acc, int P, int block,
                           hipStream_t stream);

@@ -61,6 +61,25 @@ class _State(ctypes.Structure):
                 ("age_a", ctypes.c_void_p), ("age_c", ctypes.c_void_p)]
 
 
+class _GradState(ctypes.Structure):
+    _fields_ = [("mean_a", ctypes.c_void_p), ("var_a", ctypes.c_void_p),
+                ("mean_c", ctypes.c_void_p), ("var_c", ctypes.c_void_p)]
+
+
+class Instance(ctypes.Structure):
+    """dsgm_instance"""
+    _fields_ = [("shape", Shape), ("frames", ctypes.c_void_p), ("state", _State),
+                ("masks", ctypes.c_void_p), ("bg", ctypes.c_void_p)]
+
+
+class BatchPlan(ctypes.Structure):
+    """dsgm_batch_plan (host handle)"""
+    _fields_ = [("device_plan", ctypes.c_void_p), ("n_items", ctypes.c_int64),
+                ("total_elements", ctypes.c_int64), ("n_instances", ctypes.c_int32),
+                ("in_dtype", ctypes.c_int32), ("acc", ctypes.c_int32), ("vector", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("has_bg", ctypes.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -74,12 +93,23 @@ def _load():
                                  ctypes.POINTER(_State), vp, vp, vp, i32, vp, vp]
     lib.dsgm_ckpt_bytes.argtypes = [Shape, i32, i32]
     lib.dsgm_ckpt_bytes.restype = ctypes.c_size_t
+    lib.dsgm_workspace_bytes.argtypes = [Shape, i32]
+    lib.dsgm_workspace_bytes.restype = ctypes.c_size_t
+    lib.dsgm_backward.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params), vp, i32, vp,
+                                  ctypes.POINTER(_GradState), vp, ctypes.POINTER(_GradState), vp,
+                                  vp, ctypes.c_size_t, vp]
+    lib.dsgm_batch_plan_bytes.argtypes = [ctypes.POINTER(Instance), i32, i32, i32]
+    lib.dsgm_batch_plan_bytes.restype = ctypes.c_size_t
+    lib.dsgm_plan_batched.argtypes = [ctypes.POINTER(Instance), i32, i32, i32, vp, ctypes.c_size_t,
+                                      ctypes.POINTER(BatchPlan), vp]
+    lib.dsgm_forward_batched.argtypes = [ctypes.POINTER(BatchPlan), ctypes.POINTER(Params), vp]
     lib.dsgm_status_string.argtypes = [ctypes.c_int]
     lib.dsgm_status_string.restype = ctypes.c_char_p
     lib.dsgm_last_error.restype = ctypes.c_char_p
     lib.dsgm_set_launch.argtypes = [i32, i32]
     for f in ("dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
-              "dsgm_version", "dsgm_set_launch"):
+              "dsgm_backward", "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_version",
+              "dsgm_set_launch"):
         getattr(lib, f).restype = ctypes.c_int
     del i64
     return lib
@@ -89,8 +119,9 @@ lib = _load()
 
 # names of every C entry point declared in include/dsgm.h
 EXPORTS = ["dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
-           "dsgm_ckpt_bytes", "dsgm_status_string", "dsgm_last_error", "dsgm_version",
-           "dsgm_set_launch"]
+           "dsgm_ckpt_bytes", "dsgm_workspace_bytes", "dsgm_backward", "dsgm_batch_plan_bytes",
+           "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_status_string", "dsgm_last_error",
+           "dsgm_version", "dsgm_set_launch"]
 
 
 def _check(fn: str, rc: int):
@@ -219,6 +250,49 @@ def dsgm_forward(frames: torch.Tensor, state: State, params: Params, masks: torc
                             _ptr(codes), _stream()))
 
 
+def dsgm_workspace_bytes(T: int, H: int, W: int, acc: int) -> int:
+    return int(lib.dsgm_workspace_bytes(Shape(T, H, W, W, H * W), acc))
+
+
+def _planes4(name, planes, H, W, dtype):
+    if planes is None:
+        return None
+    planes = tuple(planes)
+    if len(planes) != 4:
+        raise ValueError(f"{name}: need 4 planes (mean_a, var_a, mean_c, var_c)")
+    for t in planes:
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != H * W:
+            raise ValueError(f"{name}: need contiguous {dtype} CUDA planes of {H}x{W}")
+    return _GradState(*(t.data_ptr() for t in planes))
+
+
+def dsgm_backward(frames: torch.Tensor, params: Params, ckpt: torch.Tensor, ckpt_every: int,
+                  acc: int, grad_bg, grad_state_T, grad_frames: torch.Tensor, grad_state0,
+                  grad_var_init: torch.Tensor, workspace: torch.Tensor) -> None:
+    """Adjoint of dsgm_forward with the decisions held fixed.  ``grad_state_T``
+    and ``grad_state0`` are 4-tuples of (mean_a, var_a, mean_c, var_c) planes;
+    ``grad_var_init`` is a one-element float64 CUDA tensor."""
+    if frames.dtype not in _IN_DTYPES:
+        raise TypeError(f"frames dtype {frames.dtype} not supported")
+    sh = _frames_shape(frames)
+    adt = ACC_TORCH[acc]
+    _same_layout("grad_bg", grad_bg, frames, adt)
+    _same_layout("grad_frames", grad_frames, frames, adt)
+    gsT = _planes4("grad_state_T", grad_state_T, sh.H, sh.W, adt)
+    gs0 = _planes4("grad_state0", grad_state0, sh.H, sh.W, adt)
+    if grad_var_init.dtype != torch.float64 or not grad_var_init.is_cuda or grad_var_init.numel() != 1:
+        raise ValueError("grad_var_init: need a one-element float64 CUDA tensor")
+    need = dsgm_workspace_bytes(sh.T, sh.H, sh.W, acc)
+    if workspace.dtype != torch.uint8 or not workspace.is_cuda or workspace.numel() < need:
+        raise ValueError(f"workspace: need a CUDA uint8 tensor of at least {need} bytes")
+    _check("dsgm_backward",
+           lib.dsgm_backward(_ptr(frames), _IN_DTYPES[frames.dtype], sh, acc, ctypes.byref(params),
+                             _ptr(ckpt), int(ckpt_every), _ptr(grad_bg),
+                             ctypes.byref(gsT) if gsT is not None else None, _ptr(grad_frames),
+                             ctypes.byref(gs0) if gs0 is not None else None, _ptr(grad_var_init),
+                             _ptr(workspace), workspace.numel(), _stream()))
+
+
 # ------------------------------------------------------------------ convenience
 def forward(frames: torch.Tensor, state: State, params: Params, *, bg: bool = False,
             codes: bool = False, ckpt_every: int = 0) -> dict:
@@ -236,3 +310,117 @@ def forward(frames: torch.Tensor, state: State, params: Params, *, bg: bool = Fa
     dsgm_forward(frames, state, params, out["masks"], out.get("bg"), out.get("ckpt"), ckpt_every,
                  out.get("codes"))
     return out
+
+
+def backward(frames: torch.Tensor, params: Params, ckpt: torch.Tensor, ckpt_every: int, acc: int,
+             grad_bg=None, grad_state_T=None) -> dict:
+    """Allocate the gradients and call dsgm_backward."""
+    T, H, W = frames.shape
+    adt = ACC_TORCH[acc]
+    gx = torch.empty_strided(frames.shape, frames.stride(), dtype=adt, device=frames.device)
+    gs0 = tuple(torch.empty((H, W), dtype=adt, device=frames.device) for _ in range(4))
+    gvi = torch.empty((1,), dtype=torch.float64, device=frames.device)
+    ws = torch.empty(max(dsgm_workspace_bytes(T, H, W, acc), 1), dtype=torch.uint8,
+                     device=frames.device)
+    dsgm_backward(frames, params, ckpt, ckpt_every, acc, grad_bg, grad_state_T, gx, gs0, gvi, ws)
+    return {"grad_frames": gx, "grad_state0": gs0, "grad_var_init": gvi, "workspace": ws}
+
+
+def _like_frames(t, frames, dtype):
+    """t (or zeros) in the frames' layout and the given dtype."""
+    out = torch.empty_strided(frames.shape, frames.stride(), dtype=dtype, device=frames.device)
+    if t is None:
+        return None
+    out.copy_(t)
+    return out
+
+
+class DSGMFunction(torch.autograd.Function):
+    """Differentiable DSGM forward (Sec. 2.2-2.3 of arXiv:1702.05156).
+
+    apply(frames, mean_a, var_a, mean_c, var_c, age_a, age_c, var_init, params, ckpt_every)
+    returns (masks, bg, mean_a_T, var_a_T, mean_c_T, var_c_T, age_a_T, age_c_T).
+    The input state is not modified.  masks and ages are not differentiable;
+    the gradient flows to frames, the four float planes and var_init (a 0-d or
+    one-element tensor), with the decisions held at the forward pass's values.
+    theta_s, theta_d and the floors get no gradient (it is zero almost
+    everywhere).
+    """
+
+    @staticmethod
+    def forward(ctx, frames, mean_a, var_a, mean_c, var_c, age_a, age_c, var_init, params,
+                ckpt_every=32):
+        p = Params(*(getattr(params, n) for n, _ in Params._fields_))
+        p.var_init = float(var_init.detach().reshape(()).item()) if torch.is_tensor(var_init) \
+            else float(var_init)
+        st = State(mean_a.detach().clone(), var_a.detach().clone(), mean_c.detach().clone(),
+                   var_c.detach().clone(), age_a.detach().clone(), age_c.detach().clone())
+        out = forward(frames.detach(), st, p, bg=True, ckpt_every=ckpt_every)
+        ctx.save_for_backward(frames, out["ckpt"])
+        ctx.params, ctx.K, ctx.acc = p, ckpt_every, st.acc
+        ctx.var_init_like = var_init if torch.is_tensor(var_init) else None
+        ctx.mark_non_differentiable(out["masks"], st.age_a, st.age_c)
+        return (out["masks"], out["bg"], st.mean_a, st.var_a, st.mean_c, st.var_c, st.age_a,
+                st.age_c)
+
+    @staticmethod
+    def backward(ctx, g_masks, g_bg, g_mA, g_vA, g_mC, g_vC, g_aA, g_aC):
+        frames, ckpt = ctx.saved_tensors
+        adt = ACC_TORCH[ctx.acc]
+        gbg = _like_frames(g_bg, frames, adt)
+        gsT = None
+        if any(g is not None for g in (g_mA, g_vA, g_mC, g_vC)):
+            ref = frames.new_zeros((frames.shape[1], frames.shape[2]), dtype=adt)
+            gsT = tuple((g if g is not None else ref).to(adt).contiguous()
+                        for g in (g_mA, g_vA, g_mC, g_vC))
+        r = backward(frames, ctx.params, ckpt, ctx.K, ctx.acc, gbg, gsT)
+        gx = r["grad_frames"].to(frames.dtype)
+        gvi = None
+        if ctx.var_init_like is not None:
+            gvi = r["grad_var_init"].to(ctx.var_init_like.dtype).reshape(ctx.var_init_like.shape)
+        gs = r["grad_state0"]
+        return (gx, gs[0], gs[1], gs[2], gs[3], None, None, gvi, None, None)
+
+
+# ------------------------------------------------------------------ batched
+def _instance(frames: torch.Tensor, state: State, masks: torch.Tensor, bg=None) -> Instance:
+    sh = _frames_shape(frames)
+    _same_layout("masks", masks, frames, torch.uint8)
+    _same_layout("bg", bg, frames, ACC_TORCH[state.acc])
+    return Instance(sh, frames.data_ptr(), _cstate(state, sh.H, sh.W), masks.data_ptr(),
+                    None if bg is None else bg.data_ptr())
+
+
+class Batch:
+    """Many independent instances planned for one persistent launch.
+
+    ``items`` is a list of (frames, state, masks, bg-or-None); every tensor is
+    kept alive by this object.  ``run(params)`` calls dsgm_forward_batched on the
+    current stream (capturable into a CUDA/HIP graph).
+    """
+
+    def __init__(self, items, in_dtype=None, acc=None):
+        self.items = list(items)
+        if not self.items:
+            raise ValueError("empty batch")
+        fr0, st0 = self.items[0][0], self.items[0][1]
+        self.in_dtype = _IN_DTYPES[fr0.dtype] if in_dtype is None else in_dtype
+        self.acc = st0.acc if acc is None else acc
+        for fr, st, *_ in self.items:
+            if _IN_DTYPES[fr.dtype] != self.in_dtype or st.acc != self.acc:
+                raise ValueError("all instances of a batch share the frame and state dtypes")
+        arr = (Instance * len(self.items))(*(_instance(*it) for it in self.items))
+        self._arr = arr
+        nbytes = int(lib.dsgm_batch_plan_bytes(arr, len(self.items), self.in_dtype, self.acc))
+        if nbytes == 0:
+            raise DSGMError("dsgm_batch_plan_bytes", -1, lib.dsgm_last_error().decode())
+        self.plan_buffer = torch.empty(nbytes, dtype=torch.uint8, device=fr0.device)
+        self.plan = BatchPlan()
+        _check("dsgm_plan_batched",
+               lib.dsgm_plan_batched(arr, len(self.items), self.in_dtype, self.acc,
+                                     _ptr(self.plan_buffer), nbytes, ctypes.byref(self.plan),
+                                     _stream()))
+
+    def run(self, params: Params) -> None:
+        _check("dsgm_forward_batched",
+               lib.dsgm_forward_batched(ctypes.byref(self.plan), ctypes.byref(params), _stream()))

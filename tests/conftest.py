@@ -27,3 +27,18 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _release_gpu_memory(request):
+    """Return cached device memory after each GPU test (the full-size tests
+    each allocate tens to hundreds of GB)."""
+    yield
+    if "gpu" in request.keywords:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+        except Exception:
+            pass

@@ -120,3 +120,56 @@ def test_set_launch_validation():
     assert lib.dsgm_set_launch(100, 0) == -1
     assert lib.dsgm_set_launch(64, 3) == -1
     assert lib.dsgm_set_launch(0, 0) == 0
+
+
+def _bwd(frames=FAKE, shape=(4, 8, 8, 8, 64), ckpt=FAKE, K=2, gfr=FAKE, gs0="ok", gvi=FAKE,
+         ws=FAKE, ws_bytes=1 << 20, acc=0, in_dtype=0):
+    p = dsgm.dsgm_params_default(2.0)
+    g = dsgm._GradState(FAKE, FAKE, FAKE, FAKE) if gs0 == "ok" else gs0
+    return lib.dsgm_backward(frames, in_dtype, dsgm.Shape(*shape), acc, ctypes.byref(p), ckpt, K,
+                             None, None, gfr, ctypes.byref(g) if g is not None else None, gvi,
+                             ws, ws_bytes, None)
+
+
+def test_backward_validation():
+    assert _bwd(ws_bytes=16) == -5                       # DSGM_E_WORKSPACE
+    assert _bwd(ws=None) == -1
+    assert _bwd(gvi=None) == -1
+    assert _bwd(ckpt=None) == -1
+    assert _bwd(K=0) == -1
+    assert _bwd(gfr=None) == -1
+    assert _bwd(gs0=None) == -1
+    assert _bwd(gs0=dsgm._GradState(FAKE, None, FAKE, FAKE)) == -1
+    assert _bwd(frames=FAKE + 3) == -4
+    assert _bwd(in_dtype=0, acc=1) == -3
+    sh = dsgm.Shape(4, 8, 8, 8, 64)
+    assert lib.dsgm_workspace_bytes(sh, 0) == 512 + 4096
+    assert lib.dsgm_workspace_bytes(sh, 9) == 0
+
+
+def _inst(T=4, H=8, W=8, ptr=FAKE, bg=None):
+    return dsgm.Instance(dsgm.Shape(T, H, W, W, H * W), ptr, _state(ptr), ptr, bg)
+
+
+def test_batched_validation():
+    one = (dsgm.Instance * 2)(_inst(), _inst(T=3, H=4, W=12))
+    n = lib.dsgm_batch_plan_bytes(one, 2, 1, 1)
+    # header + 2 descriptors (padded) + items: 8*8/4 = 16 groups -> 1 item; 4*12/4 -> 1 item
+    assert n == 256 + 256 + 256
+    assert lib.dsgm_batch_plan_bytes(None, 2, 1, 1) == 0
+    bad = (dsgm.Instance * 1)(_inst(ptr=FAKE + 2))
+    assert lib.dsgm_batch_plan_bytes(bad, 1, 1, 1) == 0   # misaligned f32 frames
+    neg = (dsgm.Instance * 1)(_inst(T=-1))
+    assert lib.dsgm_batch_plan_bytes(neg, 1, 1, 1) == 0
+    plan = dsgm.BatchPlan()
+    assert lib.dsgm_plan_batched(one, 2, 1, 1, None, 1 << 20, ctypes.byref(plan), None) == -1
+    assert lib.dsgm_plan_batched(one, 2, 1, 1, FAKE, 16, ctypes.byref(plan), None) == -5
+    assert lib.dsgm_plan_batched(one, 2, 1, 1, FAKE + 8, 1 << 20, ctypes.byref(plan), None) == -4
+    p = dsgm.dsgm_params_default(2.0)
+    assert lib.dsgm_forward_batched(None, ctypes.byref(p), None) == -1
+    assert lib.dsgm_forward_batched(ctypes.byref(plan), ctypes.byref(p), None) == -1  # not planned
+    plan.device_plan = FAKE
+    plan.vector = 3
+    assert lib.dsgm_forward_batched(ctypes.byref(plan), ctypes.byref(p), None) == -1
+    plan.vector, plan.n_items = 4, 0
+    assert lib.dsgm_forward_batched(ctypes.byref(plan), ctypes.byref(p), None) == 0  # nothing to do

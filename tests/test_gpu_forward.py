@@ -213,3 +213,57 @@ def test_full_size_f64_sampled_bit_exact():
     # a property that holds at any size: masks are 0/255 everywhere
     assert int(((masks != 0) & (masks != 255)).sum()) == 0
     del fr, masks
+
+
+def _certify_fp32(codes_gpu, ref, tol_margin=1e-5):
+    """Decision certification for a reduced-precision run.  For every pixel
+    whose decision codes differ from the FP64 oracle's, the first differing
+    frame must differ in a decision whose FP64 margin is within tol_margin of
+    its threshold (the A test, the C test, or the background test); a swap or
+    reset can only differ after a differing match decision.  Returns the
+    boolean mask of diverged pixels (structural decisions differ)."""
+    c_gpu = codes_gpu.astype(np.int32)
+    c_ref = ref["codes"].astype(np.int32)
+    m = ref["margins"]
+    T, N = c_ref.shape
+    struct = (c_gpu & 0x0F) != (c_ref & 0x0F)
+    diverged = struct.any(axis=0)
+    first = np.where(diverged, struct.argmax(axis=0), T)
+    for j in np.nonzero(diverged)[0]:
+        t = first[j]
+        a_differs = (c_gpu[t, j] & 1) != (c_ref[t, j] & 1)
+        mg = abs(m[t, j, 0]) if a_differs else abs(m[t, j, 1])
+        assert mg <= tol_margin, (j, t, c_gpu[t, j], c_ref[t, j], m[t, j])
+    # foreground flips before the pixel diverges must be background-test near ties
+    fgdiff = ((c_gpu & 16) != (c_ref & 16)) & (np.arange(T)[:, None] < first[None, :])
+    for t, j in zip(*np.nonzero(fgdiff)):
+        assert abs(m[t, j, 2]) <= tol_margin, (t, j, m[t, j])
+    return diverged
+
+
+@pytest.mark.parametrize("in_dtype", [torch.float32, torch.bfloat16])
+def test_fp32_state_certified_against_oracle(in_dtype):
+    """FP32 state and arithmetic on the paper-size sequence (320x240x500): the
+    oracle runs in FP64 on the same values (frames on the storage grid, state
+    on the FP32 grid).  Every pixel whose decisions differ is certified as a
+    near tie; at most 1e-3 of the pixels may diverge; the others must agree
+    to |dm| <= 1e-5 and |dv| <= 1e-5 * max(v, var_init) over all frames."""
+    T, H, W, seed = 500, 240, 320, 31
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(seed, T, H, W, in_dtype, torch.float32)
+    x, s0 = G.host_case(seed, T, H, W, in_dtype, torch.float32)
+    out = dsgm.forward(fr, st, p, bg=True, codes=True)
+    torch.cuda.synchronize()
+    ref = oracle.forward(x, s0, G.oracle_params(p), margins=True)
+    div = _certify_fp32(G.flat(out["codes"]), ref)
+    assert div.mean() <= 1e-3, div.mean()
+    ok = ~div
+    bg = G.flat(out["bg"])
+    assert np.max(np.abs(bg[:, ok] - ref["bg"][:, ok])) <= 1e-5
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "mean_c"):
+        assert np.max(np.abs(hs[k][ok] - ref[k][ok])) <= 1e-5, k
+    for k in ("var_a", "var_c"):
+        assert np.max(np.abs(hs[k][ok] - ref[k][ok]) / np.maximum(ref[k][ok], p.var_init)) <= 1e-5, k
+    for k in ("age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k][ok], ref[k][ok])
