@@ -138,9 +138,10 @@ int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_
  *   masks      T x H x W uint8, 0 = background, 255 = foreground (required)
  *   bg         T x H x W of the accumulation type: mean_A after each frame
  *              (optional, NULL to skip)
- *   ckpt       checkpoint buffer of dsgm_ckpt_bytes(shape, acc, ckpt_every)
- *              bytes: the state before frames 0, K, 2K, ... (K = ckpt_every),
- *              used by dsgm_backward (optional, NULL to skip)
+ *   ckpt       checkpoint buffer of ckpt_bytes >= dsgm_ckpt_bytes(shape, acc,
+ *              ckpt_every) bytes (else DSGM_E_WORKSPACE): the state before
+ *              frames 0, K, 2K, ... (K = ckpt_every), used by dsgm_backward
+ *              (optional, NULL to skip)
  *   codes      T x H x W uint8 decision codes (DSGM_CODE_* bits; optional)
  * With ACC_F64 the arithmetic is IEEE binary64, rounded after every operation
  * (no fused multiply-add), and the results are bit-identical to a scalar FP64
@@ -148,8 +149,8 @@ int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_
  */
 int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
                  const dsgm_params* params /* host */, dsgm_state* state /* host struct */,
-                 uint8_t* masks, void* bg, void* ckpt, int32_t ckpt_every, uint8_t* codes,
-                 hipStream_t stream);
+                 uint8_t* masks, void* bg, void* ckpt, size_t ckpt_bytes, int32_t ckpt_every,
+                 uint8_t* codes, hipStream_t stream);
 
 /* bytes of the checkpoint buffer for dsgm_forward/dsgm_backward (0 on bad args) */
 size_t dsgm_ckpt_bytes(dsgm_shape shape, dsgm_acc acc, int32_t ckpt_every);
@@ -169,7 +170,8 @@ size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc);
  * ckpt_every frames are recomputed from `ckpt`, which dsgm_forward wrote with
  * the same frames, params, shape and ckpt_every, and swept backwards.
  *   frames         as given to dsgm_forward
- *   ckpt           dsgm_ckpt_bytes(shape, acc, ckpt_every) bytes (device)
+ *   ckpt           ckpt_bytes >= dsgm_ckpt_bytes(shape, acc, ckpt_every) bytes
+ *                  (device; smaller returns DSGM_E_WORKSPACE)
  *   grad_bg        T x H x W, accumulation type, strided like the frames (NULL = zero)
  *   grad_state_T   upstream gradient of the final planes (host struct or NULL = zero)
  *   grad_frames    T x H x W, accumulation type, strided like the frames (out)
@@ -184,8 +186,9 @@ size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc);
  * evaluation of the same chain rule in the same order.
  */
 int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
-                  const dsgm_params* params /* host */, const void* ckpt, int32_t ckpt_every,
-                  const void* grad_bg, const dsgm_grad_state* grad_state_T /* host, or NULL */,
+                  const dsgm_params* params /* host */, const void* ckpt, size_t ckpt_bytes,
+                  int32_t ckpt_every, const void* grad_bg,
+                  const dsgm_grad_state* grad_state_T /* host, or NULL */,
                   void* grad_frames, dsgm_grad_state* grad_state0 /* host */,
                   double* grad_var_init, void* workspace, size_t workspace_bytes,
                   hipStream_t stream);

@@ -251,7 +251,8 @@ int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_
 
 int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
                  const dsgm_params* params, dsgm_state* state, uint8_t* masks, void* bg,
-                 void* ckpt, int32_t ckpt_every, uint8_t* codes, hipStream_t stream) {
+                 void* ckpt, size_t ckpt_bytes, int32_t ckpt_every, uint8_t* codes,
+                 hipStream_t stream) {
   int rc;
   if ((rc = check_types(in_dtype, acc))) return rc;
   if ((rc = check_params(params))) return rc;
@@ -266,6 +267,9 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
       !state->age_c)
     return fail(DSGM_E_ARG, "a state plane is NULL");
   if (ckpt && ckpt_every < 1) return fail(DSGM_E_ARG, "ckpt_every = %d < 1", ckpt_every);
+  if (ckpt && ckpt_bytes < dsgm_ckpt_bytes(shape, acc, ckpt_every))
+    return fail(DSGM_E_WORKSPACE, "checkpoint buffer of %zu bytes, %zu needed", ckpt_bytes,
+                dsgm_ckpt_bytes(shape, acc, ckpt_every));
   const void* ptrs[11] = {frames, masks, bg, codes, state->mean_a, state->var_a,
                           state->mean_c, state->var_c, state->age_a, state->age_c, ckpt};
   const size_t elem[11] = {ie, 1, ae, 1, ae, ae, ae, ae, 1, 1, 256};
@@ -323,8 +327,8 @@ size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc) {
 }
 
 int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
-                  const dsgm_params* params, const void* ckpt, int32_t ckpt_every,
-                  const void* grad_bg, const dsgm_grad_state* grad_state_T, void* grad_frames,
+                  const dsgm_params* params, const void* ckpt, size_t ckpt_bytes,
+                  int32_t ckpt_every, const void* grad_bg, const dsgm_grad_state* grad_state_T, void* grad_frames,
                   dsgm_grad_state* grad_state0, double* grad_var_init, void* workspace,
                   size_t workspace_bytes, hipStream_t stream) {
   int rc;
@@ -352,6 +356,9 @@ int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, 
     if (!grad_frames) return fail(DSGM_E_ARG, "grad_frames is NULL");
     if (!ckpt) return fail(DSGM_E_ARG, "ckpt is NULL");
     if (ckpt_every < 1) return fail(DSGM_E_ARG, "ckpt_every = %d < 1", ckpt_every);
+    if (ckpt_bytes < dsgm_ckpt_bytes(shape, acc, ckpt_every))
+      return fail(DSGM_E_WORKSPACE, "checkpoint buffer of %zu bytes, %zu needed", ckpt_bytes,
+                  dsgm_ckpt_bytes(shape, acc, ckpt_every));
   }
   const void* ptrs[14] = {frames, grad_bg, grad_frames, workspace, grad_var_init, ckpt,
                           grad_state0 ? grad_state0->mean_a : nullptr,

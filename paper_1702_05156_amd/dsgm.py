@@ -89,15 +89,16 @@ def _load():
     lib.dsgm_params_default.argtypes = [ctypes.POINTER(Params), ctypes.c_double, i32]
     lib.dsgm_state_init_from_frame.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params),
                                                ctypes.POINTER(_State), vp]
+    sz = ctypes.c_size_t
     lib.dsgm_forward.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params),
-                                 ctypes.POINTER(_State), vp, vp, vp, i32, vp, vp]
+                                 ctypes.POINTER(_State), vp, vp, vp, sz, i32, vp, vp]
     lib.dsgm_ckpt_bytes.argtypes = [Shape, i32, i32]
     lib.dsgm_ckpt_bytes.restype = ctypes.c_size_t
     lib.dsgm_workspace_bytes.argtypes = [Shape, i32]
     lib.dsgm_workspace_bytes.restype = ctypes.c_size_t
-    lib.dsgm_backward.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params), vp, i32, vp,
+    lib.dsgm_backward.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params), vp, sz, i32, vp,
                                   ctypes.POINTER(_GradState), vp, ctypes.POINTER(_GradState), vp,
-                                  vp, ctypes.c_size_t, vp]
+                                  vp, sz, vp]
     lib.dsgm_batch_plan_bytes.argtypes = [ctypes.POINTER(Instance), i32, i32, i32]
     lib.dsgm_batch_plan_bytes.restype = ctypes.c_size_t
     lib.dsgm_plan_batched.argtypes = [ctypes.POINTER(Instance), i32, i32, i32, vp, ctypes.c_size_t,
@@ -239,15 +240,14 @@ def dsgm_forward(frames: torch.Tensor, state: State, params: Params, masks: torc
     _same_layout("masks", masks, frames, torch.uint8)
     _same_layout("bg", bg, frames, ACC_TORCH[acc])
     _same_layout("codes", codes, frames, torch.uint8)
-    if ckpt is not None:
-        need = dsgm_ckpt_bytes(sh.T, sh.H, sh.W, acc, ckpt_every)
-        if ckpt.dtype != torch.uint8 or not ckpt.is_cuda or ckpt.numel() < need:
-            raise ValueError(f"ckpt: need a CUDA uint8 tensor of at least {need} bytes")
+    if ckpt is not None and (ckpt.dtype != torch.uint8 or not ckpt.is_cuda):
+        raise ValueError("ckpt: need a CUDA uint8 tensor")
     cs = _cstate(state, sh.H, sh.W)
     _check("dsgm_forward",
            lib.dsgm_forward(_ptr(frames), _IN_DTYPES[frames.dtype], sh, acc, ctypes.byref(params),
-                            ctypes.byref(cs), _ptr(masks), _ptr(bg), _ptr(ckpt), int(ckpt_every),
-                            _ptr(codes), _stream()))
+                            ctypes.byref(cs), _ptr(masks), _ptr(bg), _ptr(ckpt),
+                            0 if ckpt is None else ckpt.numel(), int(ckpt_every), _ptr(codes),
+                            _stream()))
 
 
 def dsgm_workspace_bytes(T: int, H: int, W: int, acc: int) -> int:
@@ -285,9 +285,12 @@ def dsgm_backward(frames: torch.Tensor, params: Params, ckpt: torch.Tensor, ckpt
     need = dsgm_workspace_bytes(sh.T, sh.H, sh.W, acc)
     if workspace.dtype != torch.uint8 or not workspace.is_cuda or workspace.numel() < need:
         raise ValueError(f"workspace: need a CUDA uint8 tensor of at least {need} bytes")
+    if ckpt is not None and (ckpt.dtype != torch.uint8 or not ckpt.is_cuda):
+        raise ValueError("ckpt: need a CUDA uint8 tensor")
     _check("dsgm_backward",
            lib.dsgm_backward(_ptr(frames), _IN_DTYPES[frames.dtype], sh, acc, ctypes.byref(params),
-                             _ptr(ckpt), int(ckpt_every), _ptr(grad_bg),
+                             _ptr(ckpt), 0 if ckpt is None else ckpt.numel(), int(ckpt_every),
+                             _ptr(grad_bg),
                              ctypes.byref(gsT) if gsT is not None else None, _ptr(grad_frames),
                              ctypes.byref(gs0) if gs0 is not None else None, _ptr(grad_var_init),
                              _ptr(workspace), workspace.numel(), _stream()))

@@ -65,13 +65,13 @@ def _state(ptr=FAKE):
 
 
 def _fwd(frames=FAKE, in_dtype=0, shape=(4, 8, 8, 8, 64), acc=0, params=None, state="ok",
-         masks=FAKE, bg=None, ckpt=None, K=0, codes=None):
+         masks=FAKE, bg=None, ckpt=None, K=0, codes=None, ckpt_bytes=1 << 30):
     p = params if params is not None else dsgm.dsgm_params_default(2.0)
     st = _state() if state == "ok" else state
     return lib.dsgm_forward(frames, in_dtype, dsgm.Shape(*shape), acc,
                             ctypes.byref(p) if p is not False else None,
-                            ctypes.byref(st) if st is not None else None, masks, bg, ckpt, K,
-                            codes, None)
+                            ctypes.byref(st) if st is not None else None, masks, bg, ckpt,
+                            ckpt_bytes, K, codes, None)
 
 
 def test_forward_validation():
@@ -90,6 +90,7 @@ def test_forward_validation():
     assert _fwd(frames=FAKE + 4) == -4                   # f64 frames not 8-aligned
     assert _fwd(bg=FAKE + 2) == -4
     assert _fwd(ckpt=FAKE, K=0) == -1
+    assert _fwd(ckpt=FAKE, K=2, ckpt_bytes=100) == -5     # checkpoint buffer too small
     for bad in (dict(age_max=0), dict(age_max=256), dict(weight_rule=2), dict(mask_rule=-1),
                 dict(theta_s=-1.0), dict(var_init=float("nan")), dict(var_floor=float("inf"))):
         p = dsgm.dsgm_params_default(2.0)
@@ -123,16 +124,17 @@ def test_set_launch_validation():
 
 
 def _bwd(frames=FAKE, shape=(4, 8, 8, 8, 64), ckpt=FAKE, K=2, gfr=FAKE, gs0="ok", gvi=FAKE,
-         ws=FAKE, ws_bytes=1 << 20, acc=0, in_dtype=0):
+         ws=FAKE, ws_bytes=1 << 20, acc=0, in_dtype=0, ckpt_bytes=1 << 30):
     p = dsgm.dsgm_params_default(2.0)
     g = dsgm._GradState(FAKE, FAKE, FAKE, FAKE) if gs0 == "ok" else gs0
-    return lib.dsgm_backward(frames, in_dtype, dsgm.Shape(*shape), acc, ctypes.byref(p), ckpt, K,
-                             None, None, gfr, ctypes.byref(g) if g is not None else None, gvi,
+    return lib.dsgm_backward(frames, in_dtype, dsgm.Shape(*shape), acc, ctypes.byref(p), ckpt,
+                             ckpt_bytes, K, None, None, gfr, ctypes.byref(g) if g is not None else None, gvi,
                              ws, ws_bytes, None)
 
 
 def test_backward_validation():
     assert _bwd(ws_bytes=16) == -5                       # DSGM_E_WORKSPACE
+    assert _bwd(ckpt_bytes=1000) == -5                   # checkpoint buffer too small
     assert _bwd(ws=None) == -1
     assert _bwd(gvi=None) == -1
     assert _bwd(ckpt=None) == -1

@@ -195,12 +195,17 @@ def test_backward_validation_errors():
     with pytest.raises(ValueError):
         dsgm.dsgm_backward(fr, p, o["ckpt"], 2, dsgm.ACC_F64, None, None, gx, gs0, gvi, small)
     cs = dsgm._GradState(*(t.data_ptr() for t in gs0))
-    rc = dsgm.lib.dsgm_backward(fr.data_ptr(), 0, dsgm._frames_shape(fr), 0, p, o["ckpt"].data_ptr(), 2,
-                                None, None, gx.data_ptr(), cs, gvi.data_ptr(), small.data_ptr(), 16, None)
+    nck = o["ckpt"].numel()
+    rc = dsgm.lib.dsgm_backward(fr.data_ptr(), 0, dsgm._frames_shape(fr), 0, p, o["ckpt"].data_ptr(), nck,
+                                2, None, None, gx.data_ptr(), cs, gvi.data_ptr(), small.data_ptr(), 16, None)
     assert rc == -5  # DSGM_E_WORKSPACE
-    rc = dsgm.lib.dsgm_backward(fr.data_ptr(), 0, dsgm._frames_shape(fr), 0, p, None, 2,
+    rc = dsgm.lib.dsgm_backward(fr.data_ptr(), 0, dsgm._frames_shape(fr), 0, p, None, 0, 2,
                                 None, None, gx.data_ptr(), cs, gvi.data_ptr(), small.data_ptr(), 1 << 20, None)
     assert rc == -1  # no checkpoints
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    rc = dsgm.lib.dsgm_backward(fr.data_ptr(), 0, dsgm._frames_shape(fr), 0, p, o["ckpt"].data_ptr(), nck,
+                                1, None, None, gx.data_ptr(), cs, gvi.data_ptr(), ws.data_ptr(), 1 << 20, None)
+    assert rc == -5  # K = 1 needs more checkpoints than a K = 2 forward wrote
 
 
 @pytest.mark.slow
