@@ -281,6 +281,7 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   int P = pick_vector(shape, ptrs, elem, 10);
   if (ckpt && !aligned(ckpt, ae * P)) P = 1;
   if (g_vector_override && P % g_vector_override == 0) P = g_vector_override;
+  if (codes) P = 1;  // the decision-code (debug) variants run one pixel per lane
 
   dsgm::FwdArgs a;
   memset(&a, 0, sizeof(a));
@@ -315,7 +316,10 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   a.weight_rule = params->weight_rule;
   a.mask_rule = params->mask_rule;
   const int block = g_block_override ? g_block_override : 256;
-  hipError_t e = dsgm::launch_forward(a, in_dtype, acc, P, block, stream);
+  const int flags = (bg ? dsgm::FWD_BG : 0) | (codes ? dsgm::FWD_CODES : 0) |
+                    (ckpt ? dsgm::FWD_CKPT : 0) |
+                    (params->mask_rule == DSGM_MASK_PRINTED ? dsgm::FWD_PRINTED : 0);
+  hipError_t e = dsgm::launch_forward(a, in_dtype, acc, P, flags, block, stream);
   if (e != hipSuccess) return hip_fail(e, "dsgm_forward launch");
   return ok();
 }
@@ -480,7 +484,7 @@ int dsgm_plan_batched(const dsgm_instance* instances, int32_t n, dsgm_in_dtype i
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const void* fn = dsgm::batched_kernel_symbol(in_dtype, acc, P, L.bg);
+  const void* fn = dsgm::batched_kernel_symbol(in_dtype, acc, P, L.bg ? dsgm::FWD_BG : 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
   if (e != hipSuccess) return hip_fail(e, "dsgm_plan_batched: device query");
   e = hipMemcpyAsync(plan_buffer, host.data(), size_t(L.bytes), hipMemcpyHostToDevice, stream);
@@ -523,8 +527,10 @@ int dsgm_forward_batched(const dsgm_batch_plan* plan, const dsgm_params* params,
   a.age_max = params->age_max;
   a.weight_rule = params->weight_rule;
   a.mask_rule = params->mask_rule;
-  hipError_t e = dsgm::launch_batched(a, plan->in_dtype, plan->acc, plan->vector,
-                                      plan->has_bg != 0, plan->grid, stream);
+  const int flags = (plan->has_bg ? dsgm::FWD_BG : 0) |
+                    (params->mask_rule == DSGM_MASK_PRINTED ? dsgm::FWD_PRINTED : 0);
+  hipError_t e = dsgm::launch_batched(a, plan->in_dtype, plan->acc, plan->vector, flags,
+                                      plan->grid, stream);
   if (e != hipSuccess) return hip_fail(e, "dsgm_forward_batched launch");
   return ok();
 }

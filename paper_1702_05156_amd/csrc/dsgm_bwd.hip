@@ -43,7 +43,6 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
   k.var_init = Acc(a.var_init);
   k.ts_vf = k.theta_s * Acc(a.var_floor);
   k.td_mf = k.theta_d * Acc(a.mask_floor);
-  k.printed = a.mask_rule == 1;
 
   const char* __restrict__ frames = static_cast<const char*>(a.frames);
   const char* __restrict__ gbg = static_cast<const char*>(a.grad_bg);
@@ -86,14 +85,14 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
       s.aA = reinterpret_cast<const uint8_t*>(base + 4 * a.ckpt_fplane)[g];
       s.aC = reinterpret_cast<const uint8_t*>(base + 4 * a.ckpt_fplane + a.ckpt_aplane)[g];
       // replay up to the chunk (only when segments are longer than the tape)
-      for (int64_t t = s0; t < c0; ++t) (void)step_rec<Acc>(s, x_at(t), k, tbl);
+      for (int64_t t = s0; t < c0; ++t) (void)step_rec<Acc, false>(s, x_at(t), k, tbl);  // mask unused
       // replay the chunk, recording the tape
       Acc tape_d[KC];
       uint32_t tape_m[(KC + 1) / 2];
 #pragma unroll
       for (int i = 0; i < KC; ++i) {
         if (i < len) {
-          const StepRecord<Acc> r = step_rec<Acc>(s, x_at(c0 + i), k, tbl);
+          const StepRecord<Acc> r = step_rec<Acc, false>(s, x_at(c0 + i), k, tbl);
           tape_d[i] = r.d;
           const uint32_t m = uint32_t(r.idx) | (r.hitA ? 0x200u : 0u) | (r.swap ? 0x400u : 0u);
           if (i % 2 == 0)

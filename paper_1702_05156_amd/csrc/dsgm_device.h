@@ -49,7 +49,6 @@ struct StepConsts {
   Acc theta_s, theta_d, var_init;
   Acc ts_vf;  // theta_s * var_floor
   Acc td_mf;  // theta_d * mask_floor
-  bool printed;  // mask rule: reference is the intensity (true) or var_A (false)
 };
 
 // Fill one table slot.  w = 1/(a+1) (Sec. 2.2) or 1/a (appendix), u = 1 - w,
@@ -101,8 +100,9 @@ struct StepRecord {
   bool hitA, hitC, swap, fg;
 };
 
-// One frame of one pixel (state updated in place).
-template <typename Acc>
+// One frame of one pixel (state updated in place).  PRINTED selects the mask
+// rule: reference = the intensity (as printed) or var_A.
+template <typename Acc, bool PRINTED>
 __device__ __forceinline__ StepRecord<Acc> step_rec(Model<Acc>& s, const Acc x,
                                                     const StepConsts<Acc>& k,
                                                     const TableEntry<Acc>* __restrict__ tbl) {
@@ -147,7 +147,7 @@ __device__ __forceinline__ StepRecord<Acc> step_rec(Model<Acc>& s, const Acc x,
 
   const Acc dd = s.mA - x;
   const Acc qd = dd * dd;
-  const Acc ref = k.printed ? x : s.vA;
+  const Acc ref = PRINTED ? x : s.vA;
   const bool fg = !((qd <= k.theta_d * ref) | (qd <= k.td_mf));
   StepRecord<Acc> r;
   r.d = d;
@@ -161,10 +161,10 @@ __device__ __forceinline__ StepRecord<Acc> step_rec(Model<Acc>& s, const Acc x,
 
 // One frame of one pixel.  Returns the foreground flag; writes the decision
 // code to *code when CODES.
-template <typename Acc, bool CODES>
+template <typename Acc, bool CODES, bool PRINTED>
 __device__ __forceinline__ bool step(Model<Acc>& s, const Acc x, const StepConsts<Acc>& k,
                                      const TableEntry<Acc>* __restrict__ tbl, unsigned* code) {
-  const StepRecord<Acc> r = step_rec<Acc>(s, x, k, tbl);
+  const StepRecord<Acc> r = step_rec<Acc, PRINTED>(s, x, k, tbl);
   if (CODES) {
     *code = (r.hitA ? CODE_HIT_A : (r.hitC ? CODE_HIT_C : CODE_RESET)) |
             (r.swap ? CODE_SWAP : 0u) | (r.fg ? CODE_FG : 0u);

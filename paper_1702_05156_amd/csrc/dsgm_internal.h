@@ -91,13 +91,29 @@ struct BatchArgs {
   int32_t age_max, weight_rule, mask_rule;
 };
 
-const void* batched_kernel_symbol(int in_dtype, int acc, int P, bool bg);
-hipError_t launch_batched(const BatchArgs& a, int in_dtype, int acc, int P, bool bg, int grid,
+// Variant flags of the forward kernels (see dsgm_fwd_impl.h).
+enum : int { FWD_BG = 1, FWD_CODES = 2, FWD_CKPT = 4, FWD_PRINTED = 8 };
+
+// flags: FWD_BG and FWD_PRINTED only
+const void* batched_kernel_symbol(int in_dtype, int acc, int P, int flags);
+hipError_t launch_batched(const BatchArgs& a, int in_dtype, int acc, int P, int flags, int grid,
                           hipStream_t stream);
 
-// in_dtype: 0 f64, 1 f32, 2 bf16; acc: 0 f64, 1 f32; P in {1, 2, 4}
-hipError_t launch_forward(const FwdArgs& a, int in_dtype, int acc, int P, int block,
+// in_dtype: 0 f64, 1 f32, 2 bf16; acc: 0 f64, 1 f32; P in {1, 2, 4}; flags FWD_*
+hipError_t launch_forward(const FwdArgs& a, int in_dtype, int acc, int P, int flags, int block,
                           hipStream_t stream);
+
+// per (frames, state) type translation units
+#define DSGM_FWD_DECLARE(NAME)                                                              \
+  hipError_t launch_fwd_##NAME(const FwdArgs& a, int P, int flags, int block,               \
+                               hipStream_t stream);                                         \
+  const void* batched_sym_##NAME(int P, int flags);
+DSGM_FWD_DECLARE(f64_f64)
+DSGM_FWD_DECLARE(f32_f64)
+DSGM_FWD_DECLARE(bf16_f64)
+DSGM_FWD_DECLARE(f32_f32)
+DSGM_FWD_DECLARE(bf16_f32)
+#undef DSGM_FWD_DECLARE
 
 // state = (x, var_init, 1) for both models from frame 0 (uses frames, the
 // state planes, H, W, row_stride, var_init)

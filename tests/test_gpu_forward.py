@@ -122,17 +122,22 @@ def test_launch_shapes_do_not_change_results():
         for block, vec in ((0, 0), (64, 1), (128, 2), (256, 4), (192, 1)):
             dsgm.dsgm_set_launch(block, vec)
             fr, st = G.device_case(17, T, H, W)
-            out = dsgm.forward(fr, st, p, bg=True, codes=True)
+            out = dsgm.forward(fr, st, p, bg=True, ckpt_every=7)
             results.append((out, st))
     finally:
         dsgm.dsgm_set_launch(0, 0)
     torch.cuda.synchronize()
     o0, s0 = results[0]
     for o, s in results[1:]:
-        for k in ("masks", "bg", "codes"):
+        for k in ("masks", "bg", "ckpt"):
             assert torch.equal(o[k], o0[k]), k
         for a, b in zip(s.planes(), s0.planes()):
             assert torch.equal(a, b)
+    # the debug codes variant (one pixel per lane) gives the same results
+    fr, st = G.device_case(17, T, H, W)
+    oc = dsgm.forward(fr, st, p, bg=True, codes=True)
+    assert torch.equal(oc["masks"], o0["masks"]) and torch.equal(oc["bg"], o0["bg"])
+    assert torch.equal((oc["codes"] & 16) != 0, o0["masks"] == 255)
 
 
 def test_streaming_equals_fused():
