@@ -8,14 +8,17 @@
 // outputs up to the chunk, then over the chunk while recording a tape in
 // registers -- per frame the blend's d = m' - x and a 16-bit word holding the
 // table slot, hitA and swap -- and finally sweeps the chunk backwards, reading
-// the upstream gradient of bg and writing the gradient of the frame.  With
-// K <= KC each frame is replayed once; longer segments replay a prefix per
-// chunk.
+// the upstream gradient of bg and writing the gradient of the frame.  All of a
+// chunk's frame and gradient loads are issued before its arithmetic, so their
+// HBM latency overlaps.  With K <= KC each frame is replayed once; longer
+// segments replay a prefix per chunk.
 //
 // The per-pixel contribution to d/d(var_init) is accumulated in FP64 and
 // written to the workspace; reduce_pass1/2 then add the H*W contributions in a
 // fixed order with compensated (two-sum) arithmetic, so the scalar is
 // reproducible run to run and independent of the backward's launch shape.
+#include <type_traits>
+
 #include "dsgm_internal.h"
 
 namespace dsgm {
@@ -68,6 +71,49 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
 
   const int64_t T = a.T, K = a.ckpt_every;
   const int64_t nseg = (T + K - 1) / K;
+
+  // One chunk of `len` <= KC frames starting at c0, from state s: all of its
+  // frame loads are issued before the taped replay, all of its upstream bg
+  // gradient loads before the reverse sweep (FULL chunks need no per-frame
+  // guard).
+  auto chunk = [&](Model<Acc> s, const int64_t c0, const int len, auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    Acc xs[KC], gb[KC];
+#pragma unroll
+    for (int i = 0; i < KC; ++i)
+      if (FULL || i < len) xs[i] = x_at(c0 + i);
+    Acc tape_d[KC];
+    uint32_t tape_m[(KC + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+      if (FULL || i < len) {
+        const StepRecord<Acc> r = step_rec<Acc, false>(s, xs[i], k, tbl);  // mask unused
+        tape_d[i] = r.d;
+        const uint32_t m = uint32_t(r.idx) | (r.hitA ? 0x200u : 0u) | (r.swap ? 0x400u : 0u);
+        if (i % 2 == 0)
+          tape_m[i / 2] = m;
+        else
+          tape_m[i / 2] |= m << 16;
+      }
+    }
+    // the gradient loads reuse the frames' registers (dead after the replay)
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+      gb[i] = Acc(0);
+      if (HAS_GBG && (FULL || i < len))
+        gb[i] = *reinterpret_cast<const Acc*>(gbg + (c0 + i) * fs_acc + off_acc);
+    }
+#pragma unroll
+    for (int i = KC - 1; i >= 0; --i) {
+      if (FULL || i < len) {
+        const uint32_t m = (tape_m[i / 2] >> (16 * (i % 2))) & 0xFFFFu;
+        const Acc gx = reverse_step<Acc, HAS_GBG>(adj, gb[i], tape_d[i], int(m & 0x1FFu),
+                                                  (m & 0x200u) != 0, (m & 0x400u) != 0, tbl);
+        *reinterpret_cast<Acc*>(gfr + (c0 + i) * fs_acc + off_acc) = gx;
+      }
+    }
+  };
+
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t s0 = seg * K;
     const int64_t s1 = s0 + K < T ? s0 + K : T;
@@ -76,7 +122,6 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
     for (int64_t c = nchunk - 1; c >= 0; --c) {
       const int64_t c0 = s0 + c * KC;
       const int64_t c1 = c0 + KC < s1 ? c0 + KC : s1;
-      const int len = int(c1 - c0);
       Model<Acc> s;
       s.mA = reinterpret_cast<const Acc*>(base + 0 * a.ckpt_fplane)[g];
       s.vA = reinterpret_cast<const Acc*>(base + 1 * a.ckpt_fplane)[g];
@@ -84,36 +129,22 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
       s.vC = reinterpret_cast<const Acc*>(base + 3 * a.ckpt_fplane)[g];
       s.aA = reinterpret_cast<const uint8_t*>(base + 4 * a.ckpt_fplane)[g];
       s.aC = reinterpret_cast<const uint8_t*>(base + 4 * a.ckpt_fplane + a.ckpt_aplane)[g];
-      // replay up to the chunk (only when segments are longer than the tape)
-      for (int64_t t = s0; t < c0; ++t) (void)step_rec<Acc, false>(s, x_at(t), k, tbl);  // mask unused
-      // replay the chunk, recording the tape
-      Acc tape_d[KC];
-      uint32_t tape_m[(KC + 1) / 2];
+      // replay up to the chunk (only when segments are longer than the tape),
+      // eight frames of loads at a time
+      int64_t t = s0;
+      for (; t + 8 <= c0; t += 8) {
+        Acc xr[8];
 #pragma unroll
-      for (int i = 0; i < KC; ++i) {
-        if (i < len) {
-          const StepRecord<Acc> r = step_rec<Acc, false>(s, x_at(c0 + i), k, tbl);
-          tape_d[i] = r.d;
-          const uint32_t m = uint32_t(r.idx) | (r.hitA ? 0x200u : 0u) | (r.swap ? 0x400u : 0u);
-          if (i % 2 == 0)
-            tape_m[i / 2] = m;
-          else
-            tape_m[i / 2] |= m << 16;
-        }
-      }
-      // sweep it backwards
+        for (int i = 0; i < 8; ++i) xr[i] = x_at(t + i);
 #pragma unroll
-      for (int i = KC - 1; i >= 0; --i) {
-        if (i < len) {
-          const int64_t t = c0 + i;
-          const uint32_t m = (tape_m[i / 2] >> (16 * (i % 2))) & 0xFFFFu;
-          Acc gb = Acc(0);
-          if (HAS_GBG) gb = *reinterpret_cast<const Acc*>(gbg + t * fs_acc + off_acc);
-          const Acc gx = reverse_step<Acc, HAS_GBG>(adj, gb, tape_d[i], int(m & 0x1FFu),
-                                                    (m & 0x200u) != 0, (m & 0x400u) != 0, tbl);
-          *reinterpret_cast<Acc*>(gfr + t * fs_acc + off_acc) = gx;
-        }
+        for (int i = 0; i < 8; ++i) (void)step_rec<Acc, false>(s, xr[i], k, tbl);
       }
+      for (; t < c0; ++t) (void)step_rec<Acc, false>(s, x_at(t), k, tbl);
+      const int len = int(c1 - c0);
+      if (len == KC)
+        chunk(s, c0, len, std::true_type{});
+      else
+        chunk(s, c0, len, std::false_type{});
     }
   }
   static_cast<Acc*>(a.gs0_mean_a)[g] = adj.gmA;
