@@ -20,13 +20,15 @@ Secondary legs, reported under "legs" (same timing method):
            gradients ~N(0,1) (seed 2): forward and dsgm_backward throughput
   batched  512 instances of log-uniform size (seed 3), BF16 frames, FP32 state,
            one graph-captured persistent launch per step
+  largest  one 2160x3840x1344 instance (~200 GB resident), FP32 frames, FP64
+           state and arithmetic, FP32 bg and gradients: forward and backward
 
 Prints one JSON line: throughput, the roofline of the main kernel (HBM bound;
 algorithmic bytes per launch over the kernel's HIP-event duration), the
 oracle's CPU throughput on a bounded sample, and the legs.  Parity of each
 timed launch configuration against the oracle is checked by the test suite
 (test_full_size_f64_sampled_bit_exact, test_full_size_f32_forward_and_adjoint_sampled,
-test_full_size_batched_sampled).
+test_full_size_batched_sampled, test_full_size_io32_forward_and_adjoint_sampled).
 """
 from __future__ import annotations
 
@@ -216,6 +218,53 @@ def leg_adjoint(args, dsgm, sdev, torch):
     return out
 
 
+def leg_largest(args, dsgm, sdev, torch):
+    """The largest single instance: 2160 x 3840 x 1344 (11.1 G elements, ~200 GB
+    resident), FP32 frames, FP64 state and arithmetic, FP32 bg and gradient
+    arrays (decisions and state those of the FP64 path, arrays rounded once),
+    checkpoints every 32 frames, upstream gradients ~N(0,1), seed 4."""
+    T, H, W, K, seed = 1344, 2160, 3840, 32, 4
+    acc = dsgm.ACC_F64_IO32
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.frames(seed, T, H, W, torch.float32)
+    st = dsgm.State(*sdev.state(seed, H, W, torch.float64))
+    st0 = st.clone()
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    bg = torch.empty((T, H, W), dtype=torch.float32, device="cuda")
+    ck = torch.empty(dsgm.dsgm_ckpt_bytes(T, H, W, acc, K), dtype=torch.uint8, device="cuda")
+    gbg = sdev.grad_bg(seed + 100, T, H, W, torch.float32)
+    gst = sdev.grad_state(seed + 100, H, W, torch.float32)
+    gst = tuple(gst[i].contiguous() for i in range(4))
+    gx = torch.empty((T, H, W), dtype=torch.float32, device="cuda")
+    gs0 = tuple(torch.empty((H, W), dtype=torch.float32, device="cuda") for _ in range(4))
+    gvi = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(dsgm.dsgm_workspace_bytes(T, H, W, acc), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    resident = torch.cuda.memory_allocated()
+    stream = torch.cuda.current_stream()
+    steps = max(2, args.steps // 8)
+    msf, kf = timed(lambda: dsgm.dsgm_forward(fr, st, p, masks, bg, ck, K, acc=acc), steps, 1, stream)
+    for a, b in zip(st.planes(), st0.planes()):
+        a.copy_(b)
+    dsgm.dsgm_forward(fr, st, p, masks, bg, ck, K, acc=acc)
+    msb, kb = timed(lambda: dsgm.dsgm_backward(fr, p, ck, K, acc, gbg, gst, gx, gs0, gvi, ws),
+                    steps, 1, stream)
+    elems, px = T * H * W, H * W
+    ck_slots = (T + K - 1) // K
+    out = {"workload": "2160x3840x1344 fp32 frames, fp64 state, fp32 bg/gradients, K=32, seed 4",
+           "resident_bytes": int(resident),
+           "forward": {"elements_per_s": round(elems / (msf * 1e-3), 1), "ms_per_step": round(msf, 3),
+                       "roofline": roof(elems * 9 + px * 68, float(sum(kf) / len(kf))),
+                       "checkpoint_bytes_written": ck_slots * px * 34},
+           "backward": {"elements_per_s": round(elems / (msb * 1e-3), 1), "ms_per_step": round(msb, 3),
+                        "roofline": roof(elems * 12 + px * 40, float(sum(kb) / len(kb))),
+                        "checkpoint_bytes_read": ck_slots * px * 34},
+           "grad_var_init": float(gvi.item())}
+    del fr, st, st0, masks, bg, ck, gbg, gst, gx, gs0, gvi, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_shapes(seed=3, n=512):
     """Instance sizes: m = 256^u with u ~ U[0,1) (synth stream 10), width
     8*round(40 m^(1/4)), height 8*round(30 m^(1/4)), frames round(32 m^(1/2)):
@@ -273,7 +322,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="main,mixed,adjoint,batched")
+    ap.add_argument("--legs", default="main,mixed,adjoint,batched,largest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
@@ -334,6 +383,8 @@ def main():
         out_legs["adjoint"] = leg_adjoint(args, dsgm, sdev, torch)
     if "batched" in legs:
         out_legs["batched"] = leg_batched(args, dsgm, sdev, torch)
+    if "largest" in legs:
+        out_legs["largest"] = leg_largest(args, dsgm, sdev, torch)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(T, H, W, seed)
 

@@ -22,6 +22,8 @@
  *     gradients of frames and of bg) are T x H x W arrays addressed as
  *     t*frame_stride + h*row_stride + w, in elements of their own type.  State
  *     planes and their gradients are dense H x W (pitch W).
+ *   - "accumulation type" below means the state type of dsgm_acc; "array type"
+ *     the type of bg and of the gradient arrays (FP32 for F64_IO32).
  *   - Every call is asynchronous on `stream` (NULL = the null stream) and never
  *     synchronizes.  Arguments are validated on the host before any HIP call; a
  *     kernel fault surfaces as a HIP error of a later call or synchronization.
@@ -58,9 +60,15 @@ typedef enum {
 /* storage type of the frames */
 typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2 } dsgm_in_dtype;
 
-/* type of the model state and of every arithmetic operation.  Supported:
- * F64 with F64/F32/BF16 frames; F32 with F32/BF16 frames. */
-typedef enum { DSGM_ACC_F64 = 0, DSGM_ACC_F32 = 1 } dsgm_acc;
+/* type of the model state and of every arithmetic operation, and of the bulk
+ * output arrays (bg and every gradient array):
+ *   F64       state, arithmetic and arrays in FP64 (F64/F32/BF16 frames)
+ *   F32       state, arithmetic and arrays in FP32 (F32/BF16 frames)
+ *   F64_IO32  state and arithmetic in FP64, bg and gradient arrays in FP32
+ *             (F32/BF16 frames): decisions and state are those of the FP64
+ *             path, the arrays are its values rounded once to FP32, at the
+ *             memory cost of FP32 (the state is per pixel, not per frame) */
+typedef enum { DSGM_ACC_F64 = 0, DSGM_ACC_F32 = 1, DSGM_ACC_F64_IO32 = 2 } dsgm_acc;
 
 /* learning weight of a model of age a: Sec. 2.2 gives 1/(a+1); the appendix
  * computes 1/a.  The complementary weight is 1 - w in the accumulation type. */
@@ -102,7 +110,7 @@ typedef struct {
   uint8_t* age_c;
 } dsgm_state;
 
-/* gradients of the four float state planes (H x W each, accumulation type) */
+/* gradients of the four float state planes (H x W each, array type) */
 typedef struct {
   void* mean_a;
   void* var_a;
@@ -136,7 +144,7 @@ int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_
  * fuses the frames, keeping each pixel's model in registers, with results
  * bit-identical to T calls with T == 1.
  *   masks      T x H x W uint8, 0 = background, 255 = foreground (required)
- *   bg         T x H x W of the accumulation type: mean_A after each frame
+ *   bg         T x H x W of the array type: mean_A after each frame
  *              (optional, NULL to skip)
  *   ckpt       checkpoint buffer of ckpt_bytes >= dsgm_ckpt_bytes(shape, acc,
  *              ckpt_every) bytes (else DSGM_E_WORKSPACE): the state before
@@ -172,10 +180,12 @@ size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc);
  *   frames         as given to dsgm_forward
  *   ckpt           ckpt_bytes >= dsgm_ckpt_bytes(shape, acc, ckpt_every) bytes
  *                  (device; smaller returns DSGM_E_WORKSPACE)
- *   grad_bg        T x H x W, accumulation type, strided like the frames (NULL = zero)
- *   grad_state_T   upstream gradient of the final planes (host struct or NULL = zero)
- *   grad_frames    T x H x W, accumulation type, strided like the frames (out)
- *   grad_state0    gradient of the initial planes (host struct of device planes, out)
+ *   grad_bg        T x H x W, array type, strided like the frames (NULL = zero)
+ *   grad_state_T   upstream gradient of the final planes, array type (host
+ *                  struct or NULL = zero)
+ *   grad_frames    T x H x W, array type, strided like the frames (out)
+ *   grad_state0    gradient of the initial planes, array type (host struct of
+ *                  device planes, out)
  *   grad_var_init  one double on the device (out): the H*W per-pixel terms are
  *                  accumulated in FP64 and added in a fixed order with
  *                  compensated (error-free two-sum) arithmetic, so it is

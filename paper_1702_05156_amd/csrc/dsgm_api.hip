@@ -34,7 +34,10 @@ int hip_fail(hipError_t e, const char* where) {
 }
 
 size_t in_size(int d) { return d == DSGM_IN_F64 ? 8 : d == DSGM_IN_F32 ? 4 : 2; }
-size_t acc_size(int a) { return a == DSGM_ACC_F64 ? 8 : 4; }
+// element size of the model state (and of every arithmetic operation)
+size_t acc_size(int a) { return a == DSGM_ACC_F32 ? 4 : 8; }
+// element size of bg and of every gradient array
+size_t io_size(int a) { return a == DSGM_ACC_F64 ? 8 : 4; }
 
 bool aligned(const void* p, size_t n) { return (reinterpret_cast<uintptr_t>(p) % n) == 0; }
 
@@ -62,9 +65,10 @@ int check_params(const dsgm_params* p) {
 int check_types(int in_dtype, int acc) {
   if (in_dtype < DSGM_IN_F64 || in_dtype > DSGM_IN_BF16)
     return fail(DSGM_E_DTYPE, "in_dtype = %d invalid", in_dtype);
-  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32) return fail(DSGM_E_DTYPE, "acc = %d invalid", acc);
-  if (acc == DSGM_ACC_F32 && in_dtype == DSGM_IN_F64)
-    return fail(DSGM_E_DTYPE, "F64 frames with F32 accumulation is not supported");
+  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32)
+    return fail(DSGM_E_DTYPE, "acc = %d invalid", acc);
+  if (acc != DSGM_ACC_F64 && in_dtype == DSGM_IN_F64)
+    return fail(DSGM_E_DTYPE, "F64 frames need ACC_F64");
   return DSGM_OK;
 }
 
@@ -132,12 +136,12 @@ int plan_layout(const dsgm_instance* inst, int32_t n, int in_dtype, int acc, Pla
   int rc;
   if ((rc = check_types(in_dtype, acc))) return rc;
   if (n < 0 || (n > 0 && !inst)) return fail(DSGM_E_ARG, "instances: NULL or negative count");
-  const size_t ie = in_size(in_dtype), ae = acc_size(acc);
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
   int P = 4;
   L->bg = false;
   for (int32_t i = 0; i < n; ++i) {
     const dsgm_instance& I = inst[i];
-    if ((rc = check_shape(I.shape, ie > ae ? ie : ae)))
+    if ((rc = check_shape(I.shape, ie > oe ? ie : oe)))
       return fail(rc, "instance %d: %s", i, g_last_error);
     const int64_t px = I.shape.H * I.shape.W;
     if (px == 0 || I.shape.T == 0) continue;
@@ -147,7 +151,7 @@ int plan_layout(const dsgm_instance* inst, int32_t n, int in_dtype, int acc, Pla
     const void* ptrs[10] = {I.frames, I.masks, I.bg, I.state.mean_a, I.state.var_a,
                             I.state.mean_c, I.state.var_c, I.state.age_a, I.state.age_c,
                             nullptr};
-    const size_t elem[10] = {ie, 1, ae, ae, ae, ae, ae, 1, 1, 1};
+    const size_t elem[10] = {ie, 1, oe, ae, ae, ae, ae, 1, 1, 1};
     for (int k = 0; k < 9; ++k)
       if (ptrs[k] && !aligned(ptrs[k], elem[k]))
         return fail(DSGM_E_ALIGN, "instance %d: pointer %d not aligned to %zu bytes", i, k, elem[k]);
@@ -215,7 +219,7 @@ int dsgm_params_default(dsgm_params* p, double intensity_range, int32_t mask_rul
 }
 
 size_t dsgm_ckpt_bytes(dsgm_shape shape, dsgm_acc acc, int32_t ckpt_every) {
-  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32) return 0;
+  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32) return 0;
   if (ckpt_every < 1 || shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;
   const int64_t n = (shape.T + ckpt_every - 1) / ckpt_every;
   const int64_t px = shape.H * shape.W;
@@ -270,8 +274,8 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   int rc;
   if ((rc = check_types(in_dtype, acc))) return rc;
   if ((rc = check_params(params))) return rc;
-  const size_t ie = in_size(in_dtype), ae = acc_size(acc);
-  if ((rc = check_shape(shape, ie > ae ? ie : ae))) return rc;
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
+  if ((rc = check_shape(shape, ie > oe ? ie : oe))) return rc;
   if (!state) return fail(DSGM_E_ARG, "state is NULL");
   const int64_t px = shape.H * shape.W;
   if (px == 0 || shape.T == 0) return ok();
@@ -286,7 +290,7 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
                 dsgm_ckpt_bytes(shape, acc, ckpt_every));
   const void* ptrs[11] = {frames, masks, bg, codes, state->mean_a, state->var_a,
                           state->mean_c, state->var_c, state->age_a, state->age_c, ckpt};
-  const size_t elem[11] = {ie, 1, ae, 1, ae, ae, ae, ae, 1, 1, 256};
+  const size_t elem[11] = {ie, 1, oe, 1, ae, ae, ae, ae, 1, 1, 256};
   for (int i = 0; i < 11; ++i) {
     const size_t need = i == 10 ? 16 : elem[i];
     if (ptrs[i] && !aligned(ptrs[i], need))
@@ -340,7 +344,7 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
 }
 
 size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc) {
-  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32) return 0;
+  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32) return 0;
   if (shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;
   return size_t(pad256(shape.H * shape.W * 8)) + dsgm::reduce_workspace_bytes();
 }
@@ -353,8 +357,8 @@ int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, 
   int rc;
   if ((rc = check_types(in_dtype, acc))) return rc;
   if ((rc = check_params(params))) return rc;
-  const size_t ie = in_size(in_dtype), ae = acc_size(acc);
-  if ((rc = check_shape(shape, ie > ae ? ie : ae))) return rc;
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
+  if ((rc = check_shape(shape, ie > oe ? ie : oe))) return rc;
   const int64_t px = shape.H * shape.W;
   const int64_t n = shape.T * px;
   if (!grad_var_init) return fail(DSGM_E_ARG, "grad_var_init is NULL");
@@ -388,7 +392,7 @@ int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, 
                           grad_state_T ? grad_state_T->var_a : nullptr,
                           grad_state_T ? grad_state_T->mean_c : nullptr,
                           grad_state_T ? grad_state_T->var_c : nullptr};
-  const size_t elem[14] = {ie, ae, ae, 8, 8, 16, ae, ae, ae, ae, ae, ae, ae, ae};
+  const size_t elem[14] = {ie, oe, oe, 8, 8, 16, oe, oe, oe, oe, oe, oe, oe, oe};
   for (int i = 0; i < 14; ++i)
     if (ptrs[i] && !aligned(ptrs[i], elem[i]))
       return fail(DSGM_E_ALIGN, "pointer argument %d is not aligned to %zu bytes", i, elem[i]);

@@ -25,7 +25,7 @@ namespace dsgm {
 
 namespace {
 
-template <typename In, typename Acc, int KC, bool HAS_GBG, bool HAS_GST>
+template <typename In, typename Acc, typename Io, int KC, bool HAS_GBG, bool HAS_GST>
 __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
   __shared__ TableEntry<Acc> tbl[TABLE_SIZE];
   for (int i = threadIdx.x; i < TABLE_SIZE; i += blockDim.x)
@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
   const int64_t w = g - h * a.W;
   const uint32_t foff = uint32_t(h * a.row_stride + w);  // < 2^31 elements (host check)
   const uint32_t off_in = foff * uint32_t(sizeof(In));
-  const uint32_t off_acc = foff * uint32_t(sizeof(Acc));
+  const uint32_t off_io = foff * uint32_t(sizeof(Io));
 
   StepConsts<Acc> k;
   k.theta_s = Acc(a.theta_s);
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
   char* __restrict__ gfr = static_cast<char*>(a.grad_frames);
   const char* __restrict__ ck = static_cast<const char*>(a.ckpt);
   const int64_t fs_in = a.frame_stride * int64_t(sizeof(In));
-  const int64_t fs_acc = a.frame_stride * int64_t(sizeof(Acc));
+  const int64_t fs_io = a.frame_stride * int64_t(sizeof(Io));
 
   auto x_at = [&](int64_t t) {
     return to_acc<In, Acc>(*reinterpret_cast<const In*>(frames + t * fs_in + off_in));
@@ -61,10 +61,10 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
   Adjoint<Acc> adj;
   adj.gvi = 0.0;
   if (HAS_GST) {
-    adj.gmA = static_cast<const Acc*>(a.gst_mean_a)[g];
-    adj.gvA = static_cast<const Acc*>(a.gst_var_a)[g];
-    adj.gmC = static_cast<const Acc*>(a.gst_mean_c)[g];
-    adj.gvC = static_cast<const Acc*>(a.gst_var_c)[g];
+    adj.gmA = Acc(static_cast<const Io*>(a.gst_mean_a)[g]);
+    adj.gvA = Acc(static_cast<const Io*>(a.gst_var_a)[g]);
+    adj.gmC = Acc(static_cast<const Io*>(a.gst_mean_c)[g]);
+    adj.gvC = Acc(static_cast<const Io*>(a.gst_var_c)[g]);
   } else {
     adj.gmA = adj.gvA = adj.gmC = adj.gvC = Acc(0);
   }
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
     for (int i = 0; i < KC; ++i) {
       gb[i] = Acc(0);
       if (HAS_GBG && (FULL || i < len))
-        gb[i] = *reinterpret_cast<const Acc*>(gbg + (c0 + i) * fs_acc + off_acc);
+        gb[i] = Acc(*reinterpret_cast<const Io*>(gbg + (c0 + i) * fs_io + off_io));
     }
 #pragma unroll
     for (int i = KC - 1; i >= 0; --i) {
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
         const uint32_t m = (tape_m[i / 2] >> (16 * (i % 2))) & 0xFFFFu;
         const Acc gx = reverse_step<Acc, HAS_GBG>(adj, gb[i], tape_d[i], int(m & 0x1FFu),
                                                   (m & 0x200u) != 0, (m & 0x400u) != 0, tbl);
-        *reinterpret_cast<Acc*>(gfr + (c0 + i) * fs_acc + off_acc) = gx;
+        *reinterpret_cast<Io*>(gfr + (c0 + i) * fs_io + off_io) = Io(gx);  // rounded once
       }
     }
   };
@@ -147,10 +147,10 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
         chunk(s, c0, len, std::false_type{});
     }
   }
-  static_cast<Acc*>(a.gs0_mean_a)[g] = adj.gmA;
-  static_cast<Acc*>(a.gs0_var_a)[g] = adj.gvA;
-  static_cast<Acc*>(a.gs0_mean_c)[g] = adj.gmC;
-  static_cast<Acc*>(a.gs0_var_c)[g] = adj.gvC;
+  static_cast<Io*>(a.gs0_mean_a)[g] = Io(adj.gmA);
+  static_cast<Io*>(a.gs0_var_a)[g] = Io(adj.gvA);
+  static_cast<Io*>(a.gs0_mean_c)[g] = Io(adj.gmC);
+  static_cast<Io*>(a.gs0_var_c)[g] = Io(adj.gvC);
   a.gvi_px[g] = adj.gvi;
 }
 
@@ -220,19 +220,19 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_pass2(const double* __rest
   if (threadIdx.x == 0) out[0] = sh[0].s + sh[0].c;
 }
 
-template <typename In, typename Acc, int KC>
+template <typename In, typename Acc, typename Io, int KC>
 hipError_t launch_bwd_k(const BwdArgs& a, hipStream_t stream) {
   const int block = 256;
   const int64_t grid = (a.H * a.W + block - 1) / block;
   const bool gb = a.grad_bg != nullptr, gs = a.gst_mean_a != nullptr;
   if (gb && gs)
-    hipLaunchKernelGGL((bwd_kernel<In, Acc, KC, true, true>), dim3(uint32_t(grid)), dim3(block), 0, stream, a);
+    hipLaunchKernelGGL((bwd_kernel<In, Acc, Io, KC, true, true>), dim3(uint32_t(grid)), dim3(block), 0, stream, a);
   else if (gb)
-    hipLaunchKernelGGL((bwd_kernel<In, Acc, KC, true, false>), dim3(uint32_t(grid)), dim3(block), 0, stream, a);
+    hipLaunchKernelGGL((bwd_kernel<In, Acc, Io, KC, true, false>), dim3(uint32_t(grid)), dim3(block), 0, stream, a);
   else if (gs)
-    hipLaunchKernelGGL((bwd_kernel<In, Acc, KC, false, true>), dim3(uint32_t(grid)), dim3(block), 0, stream, a);
+    hipLaunchKernelGGL((bwd_kernel<In, Acc, Io, KC, false, true>), dim3(uint32_t(grid)), dim3(block), 0, stream, a);
   else
-    hipLaunchKernelGGL((bwd_kernel<In, Acc, KC, false, false>), dim3(uint32_t(grid)), dim3(block), 0, stream, a);
+    hipLaunchKernelGGL((bwd_kernel<In, Acc, Io, KC, false, false>), dim3(uint32_t(grid)), dim3(block), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -249,12 +249,15 @@ hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* ou
 
 hipError_t launch_backward(const BwdArgs& a, int in_dtype, int acc, hipStream_t stream) {
   if (acc == 0) {
-    if (in_dtype == 0) return launch_bwd_k<double, double, 16>(a, stream);
-    if (in_dtype == 1) return launch_bwd_k<float, double, 16>(a, stream);
-    if (in_dtype == 2) return launch_bwd_k<bf16_t, double, 16>(a, stream);
+    if (in_dtype == 0) return launch_bwd_k<double, double, double, 16>(a, stream);
+    if (in_dtype == 1) return launch_bwd_k<float, double, double, 16>(a, stream);
+    if (in_dtype == 2) return launch_bwd_k<bf16_t, double, double, 16>(a, stream);
   } else if (acc == 1) {
-    if (in_dtype == 1) return launch_bwd_k<float, float, 32>(a, stream);
-    if (in_dtype == 2) return launch_bwd_k<bf16_t, float, 32>(a, stream);
+    if (in_dtype == 1) return launch_bwd_k<float, float, float, 32>(a, stream);
+    if (in_dtype == 2) return launch_bwd_k<bf16_t, float, float, 32>(a, stream);
+  } else if (acc == 2) {
+    if (in_dtype == 1) return launch_bwd_k<float, double, float, 16>(a, stream);
+    if (in_dtype == 2) return launch_bwd_k<bf16_t, double, float, 16>(a, stream);
   }
   return hipErrorInvalidValue;
 }

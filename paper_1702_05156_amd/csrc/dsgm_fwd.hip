@@ -35,7 +35,7 @@ hipError_t launch_init_t(const FwdArgs& a, hipStream_t stream) {
 }  // namespace
 
 hipError_t launch_init(const FwdArgs& a, int in_dtype, int acc, hipStream_t stream) {
-  if (acc == 0) {
+  if (acc == 0 || acc == 2) {
     if (in_dtype == 0) return launch_init_t<double, double>(a, stream);
     if (in_dtype == 1) return launch_init_t<float, double>(a, stream);
     if (in_dtype == 2) return launch_init_t<bf16_t, double>(a, stream);
@@ -55,6 +55,9 @@ hipError_t launch_forward(const FwdArgs& a, int in_dtype, int acc, int P, int fl
   } else if (acc == 1) {
     if (in_dtype == 1) return launch_fwd_f32_f32(a, P, flags, block, stream);
     if (in_dtype == 2) return launch_fwd_bf16_f32(a, P, flags, block, stream);
+  } else if (acc == 2) {
+    if (in_dtype == 1) return launch_fwd_f32_f64io32(a, P, flags, block, stream);
+    if (in_dtype == 2) return launch_fwd_bf16_f64io32(a, P, flags, block, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -67,6 +70,9 @@ const void* batched_kernel_symbol(int in_dtype, int acc, int P, int flags) {
   } else if (acc == 1) {
     if (in_dtype == 1) return batched_sym_f32_f32(P, flags);
     if (in_dtype == 2) return batched_sym_bf16_f32(P, flags);
+  } else if (acc == 2) {
+    if (in_dtype == 1) return batched_sym_f32_f64io32(P, flags);
+    if (in_dtype == 2) return batched_sym_bf16_f64io32(P, flags);
   }
   return nullptr;
 }

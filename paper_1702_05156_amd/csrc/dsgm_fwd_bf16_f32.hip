@@ -3,6 +3,6 @@
 
 namespace dsgm {
 
-DSGM_FWD_INSTANTIATE(bf16_t, float, bf16_f32)
+DSGM_FWD_INSTANTIATE(bf16_t, float, float, bf16_f32)
 
 }  // namespace dsgm

@@ -3,6 +3,6 @@
 
 namespace dsgm {
 
-DSGM_FWD_INSTANTIATE(bf16_t, double, bf16_f64)
+DSGM_FWD_INSTANTIATE(bf16_t, double, double, bf16_f64)
 
 }  // namespace dsgm

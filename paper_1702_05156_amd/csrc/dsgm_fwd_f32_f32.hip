@@ -3,6 +3,6 @@
 
 namespace dsgm {
 
-DSGM_FWD_INSTANTIATE(float, float, f32_f32)
+DSGM_FWD_INSTANTIATE(float, float, float, f32_f32)
 
 }  // namespace dsgm

@@ -3,6 +3,6 @@
 
 namespace dsgm {
 
-DSGM_FWD_INSTANTIATE(float, double, f32_f64)
+DSGM_FWD_INSTANTIATE(float, double, double, f32_f64)
 
 }  // namespace dsgm

@@ -3,6 +3,6 @@
 
 namespace dsgm {
 
-DSGM_FWD_INSTANTIATE(double, double, f64_f64)
+DSGM_FWD_INSTANTIATE(double, double, double, f64_f64)
 
 }  // namespace dsgm

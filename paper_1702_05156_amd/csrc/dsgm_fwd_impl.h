@@ -130,7 +130,7 @@ __device__ __forceinline__ void store_state(char* const planes[6], int64_t soff,
   *reinterpret_cast<Vec<uint8_t, P>*>(planes[5] + soff) = aC;
 }
 
-template <typename In, typename Acc, int P, int U, int FLAGS>
+template <typename In, typename Acc, typename Io, int P, int U, int FLAGS>
 __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Acc>& k,
                                           const TableEntry<Acc>* __restrict__ tbl) {
   constexpr bool BG = (FLAGS & F_BG) != 0;
@@ -161,7 +161,7 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
   // per-lane byte offset, so loads and stores use the saddr+voffset form
   const int64_t T = j.T, fs = j.frame_stride;
   const uint32_t off_in = j.foff * uint32_t(sizeof(In));
-  const uint32_t off_acc = j.foff * uint32_t(sizeof(Acc));
+  const uint32_t off_io = j.foff * uint32_t(sizeof(Io));
   // checkpoints: the state before frames 0, K, 2K, ... into consecutive slots
   char* ck_slot = j.ckpt;
   int64_t ck_left = 0;
@@ -179,19 +179,19 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
       --ck_left;
     }
     Vec<uint8_t, P> mk;
-    Vec<Acc, P> bgv;
+    Vec<Io, P> bgv;
     Vec<uint8_t, P> cd;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       unsigned c = 0;
       const bool fg = step<Acc, CODES, PRINTED>(s[q], to_acc<In, Acc>(xin.v[q]), k, tbl, &c);
       mk.v[q] = fg ? uint8_t(255) : uint8_t(0);
-      if (BG) bgv.v[q] = s[q].mA;
+      if (BG) bgv.v[q] = Io(s[q].mA);  // rounded once when Io is narrower
       if (CODES) cd.v[q] = uint8_t(c);
     }
     const int64_t o = t * fs;
     st_stream<uint8_t, P>(reinterpret_cast<uint8_t*>(j.masks + o + j.foff), mk);
-    if (BG) st_stream<Acc, P>(reinterpret_cast<Acc*>(j.bg + o * int64_t(sizeof(Acc)) + off_acc), bgv);
+    if (BG) st_stream<Io, P>(reinterpret_cast<Io*>(j.bg + o * int64_t(sizeof(Io)) + off_io), bgv);
     if (CODES) *reinterpret_cast<Vec<uint8_t, P>*>(j.codes + o + j.foff) = cd;
   };
 
@@ -226,7 +226,7 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
   store_state<Acc, P>(j.state, j.soff, s);
 }
 
-template <typename In, typename Acc, int P, int U, int FLAGS>
+template <typename In, typename Acc, typename Io, int P, int U, int FLAGS>
 __global__ void __launch_bounds__(256) fwd_kernel(const FwdArgs a) {
   __shared__ TableEntry<Acc> tbl[TABLE_SIZE];
   fill_table<Acc>(tbl, a.weight_rule, a.age_max, a.var_init);
@@ -257,11 +257,11 @@ __global__ void __launch_bounds__(256) fwd_kernel(const FwdArgs a) {
   j.frame_stride = a.frame_stride;
   j.foff = uint32_t(h * a.row_stride + w0);  // < 2^31 elements (host check)
   j.soff = h * a.W + w0;
-  run_group<In, Acc, P, U, FLAGS>(j, k, tbl);
+  run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl);
 }
 
 // FLAGS may only hold F_BG and F_PRINTED (no codes, no checkpoints)
-template <typename In, typename Acc, int P, int U, int FLAGS>
+template <typename In, typename Acc, typename Io, int P, int U, int FLAGS>
 __global__ void __launch_bounds__(256) batched_kernel(const BatchArgs a) {
   __shared__ TableEntry<Acc> tbl[TABLE_SIZE];
   fill_table<Acc>(tbl, a.weight_rule, a.age_max, a.var_init);
@@ -297,22 +297,22 @@ __global__ void __launch_bounds__(256) batched_kernel(const BatchArgs a) {
       j.soff = h * I.W + w0;
       if constexpr ((FLAGS & F_BG) != 0) {
         if (I.bg != nullptr)  // a batch with bg outputs may hold instances without
-          run_group<In, Acc, P, U, FLAGS>(j, k, tbl);
+          run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl);
         else
-          run_group<In, Acc, P, U, FLAGS & ~F_BG>(j, k, tbl);
+          run_group<In, Acc, Io, P, U, FLAGS & ~F_BG>(j, k, tbl);
       } else {
-        run_group<In, Acc, P, U, FLAGS>(j, k, tbl);
+        run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl);
       }
     }
   }
 }
 
 // Launchers of one (In, Acc) pair, defined in the per-type translation units.
-template <typename In, typename Acc, int P, int FLAGS>
+template <typename In, typename Acc, typename Io, int P, int FLAGS>
 hipError_t launch_fwd_v(const FwdArgs& a, int block, hipStream_t stream) {
   constexpr int U = 4;
   const int64_t grid = (a.ngroups + block - 1) / block;
-  hipLaunchKernelGGL((fwd_kernel<In, Acc, P, U, FLAGS>), dim3(uint32_t(grid)), dim3(block), 0,
+  hipLaunchKernelGGL((fwd_kernel<In, Acc, Io, P, U, FLAGS>), dim3(uint32_t(grid)), dim3(block), 0,
                      stream, a);
   return hipGetLastError();
 }
@@ -320,75 +320,77 @@ hipError_t launch_fwd_v(const FwdArgs& a, int block, hipStream_t stream) {
 // runtime flags -> compile-time variant.  Decision codes are a debug output:
 // they only exist as one-pixel-per-lane variants (results do not depend on P),
 // so the caller must size the grid for P = 1 when it asks for codes.
-template <typename In, typename Acc, int P>
+template <typename In, typename Acc, typename Io, int P>
 hipError_t launch_fwd_p(const FwdArgs& a, int flags, int block, hipStream_t stream) {
   switch (flags & (F_BG | F_CKPT | F_PRINTED)) {
-    case 0: return launch_fwd_v<In, Acc, P, 0>(a, block, stream);
-    case F_BG: return launch_fwd_v<In, Acc, P, F_BG>(a, block, stream);
-    case F_CKPT: return launch_fwd_v<In, Acc, P, F_CKPT>(a, block, stream);
-    case F_BG | F_CKPT: return launch_fwd_v<In, Acc, P, F_BG | F_CKPT>(a, block, stream);
-    case F_PRINTED: return launch_fwd_v<In, Acc, P, F_PRINTED>(a, block, stream);
-    case F_BG | F_PRINTED: return launch_fwd_v<In, Acc, P, F_BG | F_PRINTED>(a, block, stream);
-    case F_CKPT | F_PRINTED: return launch_fwd_v<In, Acc, P, F_CKPT | F_PRINTED>(a, block, stream);
-    default: return launch_fwd_v<In, Acc, P, F_BG | F_CKPT | F_PRINTED>(a, block, stream);
+    case 0: return launch_fwd_v<In, Acc, Io, P, 0>(a, block, stream);
+    case F_BG: return launch_fwd_v<In, Acc, Io, P, F_BG>(a, block, stream);
+    case F_CKPT: return launch_fwd_v<In, Acc, Io, P, F_CKPT>(a, block, stream);
+    case F_BG | F_CKPT: return launch_fwd_v<In, Acc, Io, P, F_BG | F_CKPT>(a, block, stream);
+    case F_PRINTED: return launch_fwd_v<In, Acc, Io, P, F_PRINTED>(a, block, stream);
+    case F_BG | F_PRINTED: return launch_fwd_v<In, Acc, Io, P, F_BG | F_PRINTED>(a, block, stream);
+    case F_CKPT | F_PRINTED: return launch_fwd_v<In, Acc, Io, P, F_CKPT | F_PRINTED>(a, block, stream);
+    default: return launch_fwd_v<In, Acc, Io, P, F_BG | F_CKPT | F_PRINTED>(a, block, stream);
   }
 }
 
-template <typename In, typename Acc>
+template <typename In, typename Acc, typename Io>
 hipError_t launch_fwd_codes(const FwdArgs& a, int flags, int block, hipStream_t stream) {
   switch (flags & (F_BG | F_CKPT | F_PRINTED)) {
-    case 0: return launch_fwd_v<In, Acc, 1, F_CODES>(a, block, stream);
-    case F_BG: return launch_fwd_v<In, Acc, 1, F_CODES | F_BG>(a, block, stream);
-    case F_CKPT: return launch_fwd_v<In, Acc, 1, F_CODES | F_CKPT>(a, block, stream);
-    case F_BG | F_CKPT: return launch_fwd_v<In, Acc, 1, F_CODES | F_BG | F_CKPT>(a, block, stream);
-    case F_PRINTED: return launch_fwd_v<In, Acc, 1, F_CODES | F_PRINTED>(a, block, stream);
+    case 0: return launch_fwd_v<In, Acc, Io, 1, F_CODES>(a, block, stream);
+    case F_BG: return launch_fwd_v<In, Acc, Io, 1, F_CODES | F_BG>(a, block, stream);
+    case F_CKPT: return launch_fwd_v<In, Acc, Io, 1, F_CODES | F_CKPT>(a, block, stream);
+    case F_BG | F_CKPT: return launch_fwd_v<In, Acc, Io, 1, F_CODES | F_BG | F_CKPT>(a, block, stream);
+    case F_PRINTED: return launch_fwd_v<In, Acc, Io, 1, F_CODES | F_PRINTED>(a, block, stream);
     case F_BG | F_PRINTED:
-      return launch_fwd_v<In, Acc, 1, F_CODES | F_BG | F_PRINTED>(a, block, stream);
+      return launch_fwd_v<In, Acc, Io, 1, F_CODES | F_BG | F_PRINTED>(a, block, stream);
     case F_CKPT | F_PRINTED:
-      return launch_fwd_v<In, Acc, 1, F_CODES | F_CKPT | F_PRINTED>(a, block, stream);
-    default: return launch_fwd_v<In, Acc, 1, F_CODES | F_BG | F_CKPT | F_PRINTED>(a, block, stream);
+      return launch_fwd_v<In, Acc, Io, 1, F_CODES | F_CKPT | F_PRINTED>(a, block, stream);
+    default: return launch_fwd_v<In, Acc, Io, 1, F_CODES | F_BG | F_CKPT | F_PRINTED>(a, block, stream);
   }
 }
 
-template <typename In, typename Acc>
+template <typename In, typename Acc, typename Io>
 hipError_t launch_fwd_t(const FwdArgs& a, int P, int flags, int block, hipStream_t stream) {
   if (flags & F_CODES) {
     if (P != 1) return hipErrorInvalidValue;  // the caller sizes the grid for P = 1
-    return launch_fwd_codes<In, Acc>(a, flags, block, stream);
+    return launch_fwd_codes<In, Acc, Io>(a, flags, block, stream);
   }
-  if (P == 4) return launch_fwd_p<In, Acc, 4>(a, flags, block, stream);
-  if (P == 2) return launch_fwd_p<In, Acc, 2>(a, flags, block, stream);
-  return launch_fwd_p<In, Acc, 1>(a, flags, block, stream);
+  if (P == 4) return launch_fwd_p<In, Acc, Io, 4>(a, flags, block, stream);
+  if (P == 2) return launch_fwd_p<In, Acc, Io, 2>(a, flags, block, stream);
+  return launch_fwd_p<In, Acc, Io, 1>(a, flags, block, stream);
 }
 
-template <typename In, typename Acc, int P>
+template <typename In, typename Acc, typename Io, int P>
 const void* batched_symbol_p(int flags) {
   constexpr int U = 4;
   switch (flags & (F_BG | F_PRINTED)) {
-    case 0: return reinterpret_cast<const void*>(&batched_kernel<In, Acc, P, U, 0>);
-    case F_BG: return reinterpret_cast<const void*>(&batched_kernel<In, Acc, P, U, F_BG>);
-    case F_PRINTED: return reinterpret_cast<const void*>(&batched_kernel<In, Acc, P, U, F_PRINTED>);
-    default: return reinterpret_cast<const void*>(&batched_kernel<In, Acc, P, U, F_BG | F_PRINTED>);
+    case 0: return reinterpret_cast<const void*>(&batched_kernel<In, Acc, Io, P, U, 0>);
+    case F_BG: return reinterpret_cast<const void*>(&batched_kernel<In, Acc, Io, P, U, F_BG>);
+    case F_PRINTED:
+      return reinterpret_cast<const void*>(&batched_kernel<In, Acc, Io, P, U, F_PRINTED>);
+    default:
+      return reinterpret_cast<const void*>(&batched_kernel<In, Acc, Io, P, U, F_BG | F_PRINTED>);
   }
 }
 
-template <typename In, typename Acc>
+template <typename In, typename Acc, typename Io>
 const void* batched_symbol_t(int P, int flags) {
-  if (P == 4) return batched_symbol_p<In, Acc, 4>(flags);
-  if (P == 2) return batched_symbol_p<In, Acc, 2>(flags);
-  return batched_symbol_p<In, Acc, 1>(flags);
+  if (P == 4) return batched_symbol_p<In, Acc, Io, 4>(flags);
+  if (P == 2) return batched_symbol_p<In, Acc, Io, 2>(flags);
+  return batched_symbol_p<In, Acc, Io, 1>(flags);
 }
 
 }  // namespace fwd
 
 // One translation unit per (frame type, accumulation type) instantiates these.
-#define DSGM_FWD_INSTANTIATE(IN, ACC, NAME)                                                \
+#define DSGM_FWD_INSTANTIATE(IN, ACC, IO, NAME)                                            \
   hipError_t launch_fwd_##NAME(const FwdArgs& a, int P, int flags, int block,              \
                                hipStream_t stream) {                                       \
-    return fwd::launch_fwd_t<IN, ACC>(a, P, flags, block, stream);                         \
+    return fwd::launch_fwd_t<IN, ACC, IO>(a, P, flags, block, stream);                     \
   }                                                                                        \
   const void* batched_sym_##NAME(int P, int flags) {                                       \
-    return fwd::batched_symbol_t<IN, ACC>(P, flags);                                       \
+    return fwd::batched_symbol_t<IN, ACC, IO>(P, flags);                                   \
   }
 
 }  // namespace dsgm

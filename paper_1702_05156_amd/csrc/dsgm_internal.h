@@ -99,7 +99,8 @@ const void* batched_kernel_symbol(int in_dtype, int acc, int P, int flags);
 hipError_t launch_batched(const BatchArgs& a, int in_dtype, int acc, int P, int flags, int grid,
                           hipStream_t stream);
 
-// in_dtype: 0 f64, 1 f32, 2 bf16; acc: 0 f64, 1 f32; P in {1, 2, 4}; flags FWD_*
+// in_dtype: 0 f64, 1 f32, 2 bf16; acc: 0 f64, 1 f32, 2 f64 state with f32 bg and
+// gradients; P in {1, 2, 4}; flags FWD_*
 hipError_t launch_forward(const FwdArgs& a, int in_dtype, int acc, int P, int flags, int block,
                           hipStream_t stream);
 
@@ -113,6 +114,8 @@ DSGM_FWD_DECLARE(f32_f64)
 DSGM_FWD_DECLARE(bf16_f64)
 DSGM_FWD_DECLARE(f32_f32)
 DSGM_FWD_DECLARE(bf16_f32)
+DSGM_FWD_DECLARE(f32_f64io32)
+DSGM_FWD_DECLARE(bf16_f64io32)
 #undef DSGM_FWD_DECLARE
 
 // state = (x, var_init, 1) for both models from frame 0 (uses frames, the

@@ -23,14 +23,16 @@ DSGM_OK = 0
 STATUS = {0: "DSGM_OK", -1: "DSGM_E_ARG", -2: "DSGM_E_SHAPE", -3: "DSGM_E_DTYPE",
           -4: "DSGM_E_ALIGN", -5: "DSGM_E_WORKSPACE", -6: "DSGM_E_HIP", -7: "DSGM_E_UNSUPPORTED"}
 IN_F64, IN_F32, IN_BF16 = 0, 1, 2
-ACC_F64, ACC_F32 = 0, 1
+ACC_F64, ACC_F32, ACC_F64_IO32 = 0, 1, 2
 WEIGHT_EQ, WEIGHT_APPENDIX = 0, 1
 MASK_VARIANCE, MASK_PRINTED = 0, 1
 CODE_HIT_A, CODE_HIT_C, CODE_RESET, CODE_SWAP, CODE_FG = 1, 2, 4, 8, 16
 
 _IN_DTYPES = {torch.float64: IN_F64, torch.float32: IN_F32, torch.bfloat16: IN_BF16}
 _ACC_DTYPES = {torch.float64: ACC_F64, torch.float32: ACC_F32}
-ACC_TORCH = {ACC_F64: torch.float64, ACC_F32: torch.float32}
+# dtype of bg and of the gradient arrays, and of the model state, per dsgm_acc
+ACC_TORCH = {ACC_F64: torch.float64, ACC_F32: torch.float32, ACC_F64_IO32: torch.float32}
+STATE_TORCH = {ACC_F64: torch.float64, ACC_F32: torch.float32, ACC_F64_IO32: torch.float64}
 
 
 class DSGMError(RuntimeError):
@@ -181,6 +183,14 @@ class State:
         return State(f(), f(), f(), f(), u(), u())
 
 
+def _resolve_acc(state: State, acc) -> int:
+    if acc is None:
+        return state.acc
+    if STATE_TORCH[acc] != state.mean_a.dtype:
+        raise ValueError(f"acc={acc} needs a {STATE_TORCH[acc]} state, got {state.mean_a.dtype}")
+    return acc
+
+
 def _cstate(st: State, H: int, W: int) -> _State:
     acc_dt = st.mean_a.dtype
     if acc_dt not in _ACC_DTYPES:
@@ -230,13 +240,14 @@ def dsgm_ckpt_bytes(T: int, H: int, W: int, acc: int, ckpt_every: int) -> int:
 
 def dsgm_forward(frames: torch.Tensor, state: State, params: Params, masks: torch.Tensor,
                  bg: torch.Tensor | None = None, ckpt: torch.Tensor | None = None,
-                 ckpt_every: int = 0, codes: torch.Tensor | None = None) -> None:
+                 ckpt_every: int = 0, codes: torch.Tensor | None = None, acc=None) -> None:
     """Run the T frames of ``frames`` (T x H x W) through the model in ``state``
-    (updated in place); writes ``masks`` and the optional outputs."""
+    (updated in place); writes ``masks`` and the optional outputs.  ``acc``
+    defaults to the state's type (ACC_F64_IO32 must be asked for)."""
     if frames.dtype not in _IN_DTYPES:
         raise TypeError(f"frames dtype {frames.dtype} not supported")
     sh = _frames_shape(frames)
-    acc = state.acc
+    acc = _resolve_acc(state, acc)
     _same_layout("masks", masks, frames, torch.uint8)
     _same_layout("bg", bg, frames, ACC_TORCH[acc])
     _same_layout("codes", codes, frames, torch.uint8)
@@ -298,20 +309,21 @@ def dsgm_backward(frames: torch.Tensor, params: Params, ckpt: torch.Tensor, ckpt
 
 # ------------------------------------------------------------------ convenience
 def forward(frames: torch.Tensor, state: State, params: Params, *, bg: bool = False,
-            codes: bool = False, ckpt_every: int = 0) -> dict:
+            codes: bool = False, ckpt_every: int = 0, acc=None) -> dict:
     """Allocate the outputs (same layout as ``frames``) and call dsgm_forward."""
     T, H, W = frames.shape
+    acc = _resolve_acc(state, acc)
     like = lambda dt: torch.empty_strided(frames.shape, frames.stride(), dtype=dt, device=frames.device)
     out = {"masks": like(torch.uint8)}
     if bg:
-        out["bg"] = like(ACC_TORCH[state.acc])
+        out["bg"] = like(ACC_TORCH[acc])
     if codes:
         out["codes"] = like(torch.uint8)
     if ckpt_every:
-        out["ckpt"] = torch.empty(max(dsgm_ckpt_bytes(T, H, W, state.acc, ckpt_every), 1),
+        out["ckpt"] = torch.empty(max(dsgm_ckpt_bytes(T, H, W, acc, ckpt_every), 1),
                                   dtype=torch.uint8, device=frames.device)
     dsgm_forward(frames, state, params, out["masks"], out.get("bg"), out.get("ckpt"), ckpt_every,
-                 out.get("codes"))
+                 out.get("codes"), acc=acc)
     return out
 
 
@@ -341,7 +353,7 @@ def _like_frames(t, frames, dtype):
 class DSGMFunction(torch.autograd.Function):
     """Differentiable DSGM forward (Sec. 2.2-2.3 of arXiv:1702.05156).
 
-    apply(frames, mean_a, var_a, mean_c, var_c, age_a, age_c, var_init, params, ckpt_every)
+    apply(frames, mean_a, var_a, mean_c, var_c, age_a, age_c, var_init, params, ckpt_every, acc)
     returns (masks, bg, mean_a_T, var_a_T, mean_c_T, var_c_T, age_a_T, age_c_T).
     The input state is not modified.  masks and ages are not differentiable;
     the gradient flows to frames, the four float planes and var_init (a 0-d or
@@ -352,15 +364,16 @@ class DSGMFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, frames, mean_a, var_a, mean_c, var_c, age_a, age_c, var_init, params,
-                ckpt_every=32):
+                ckpt_every=32, acc=None):
         p = Params(*(getattr(params, n) for n, _ in Params._fields_))
         p.var_init = float(var_init.detach().reshape(()).item()) if torch.is_tensor(var_init) \
             else float(var_init)
         st = State(mean_a.detach().clone(), var_a.detach().clone(), mean_c.detach().clone(),
                    var_c.detach().clone(), age_a.detach().clone(), age_c.detach().clone())
-        out = forward(frames.detach(), st, p, bg=True, ckpt_every=ckpt_every)
+        acc = _resolve_acc(st, acc)
+        out = forward(frames.detach(), st, p, bg=True, ckpt_every=ckpt_every, acc=acc)
         ctx.save_for_backward(frames, out["ckpt"])
-        ctx.params, ctx.K, ctx.acc = p, ckpt_every, st.acc
+        ctx.params, ctx.K, ctx.acc = p, ckpt_every, acc
         ctx.var_init_like = var_init if torch.is_tensor(var_init) else None
         ctx.mark_non_differentiable(out["masks"], st.age_a, st.age_c)
         return (out["masks"], out["bg"], st.mean_a, st.var_a, st.mean_c, st.var_c, st.age_a,
@@ -382,14 +395,16 @@ class DSGMFunction(torch.autograd.Function):
         if ctx.var_init_like is not None:
             gvi = r["grad_var_init"].to(ctx.var_init_like.dtype).reshape(ctx.var_init_like.shape)
         gs = r["grad_state0"]
-        return (gx, gs[0], gs[1], gs[2], gs[3], None, None, gvi, None, None)
+        gs = tuple(g.to(STATE_TORCH[ctx.acc]) for g in gs)
+        return (gx, gs[0], gs[1], gs[2], gs[3], None, None, gvi, None, None, None)
 
 
 # ------------------------------------------------------------------ batched
-def _instance(frames: torch.Tensor, state: State, masks: torch.Tensor, bg=None) -> Instance:
+def _instance(frames: torch.Tensor, state: State, masks: torch.Tensor, bg=None, acc=None) -> Instance:
     sh = _frames_shape(frames)
+    acc = _resolve_acc(state, acc)
     _same_layout("masks", masks, frames, torch.uint8)
-    _same_layout("bg", bg, frames, ACC_TORCH[state.acc])
+    _same_layout("bg", bg, frames, ACC_TORCH[acc])
     return Instance(sh, frames.data_ptr(), _cstate(state, sh.H, sh.W), masks.data_ptr(),
                     None if bg is None else bg.data_ptr())
 
@@ -410,9 +425,9 @@ class Batch:
         self.in_dtype = _IN_DTYPES[fr0.dtype] if in_dtype is None else in_dtype
         self.acc = st0.acc if acc is None else acc
         for fr, st, *_ in self.items:
-            if _IN_DTYPES[fr.dtype] != self.in_dtype or st.acc != self.acc:
+            if _IN_DTYPES[fr.dtype] != self.in_dtype or st.mean_a.dtype != STATE_TORCH[self.acc]:
                 raise ValueError("all instances of a batch share the frame and state dtypes")
-        arr = (Instance * len(self.items))(*(_instance(*it) for it in self.items))
+        arr = (Instance * len(self.items))(*(_instance(*it, acc=self.acc) for it in self.items))
         self._arr = arr
         nbytes = int(lib.dsgm_batch_plan_bytes(arr, len(self.items), self.in_dtype, self.acc))
         if nbytes == 0:

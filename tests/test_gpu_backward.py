@@ -239,3 +239,65 @@ def test_full_size_f32_forward_and_adjoint_sampled():
     assert _rel_l2(g0, ref["grad_state0"]) <= 1e-5
     px = r["workspace"][: H * W * 8].view(torch.float64)[pt].cpu().numpy()
     assert _rel_l2(px, ref["grad_var_init_px"]) <= 1e-5
+
+
+def test_io32_adjoint_is_fp64_rounded_once():
+    """FP64 adjoint arithmetic with FP32 gradient arrays: every gradient equals
+    the FP64 oracle's (under the same decisions, fed the same FP32 upstream
+    values) rounded once to FP32."""
+    T, H, W, K, seed = 120, 16, 40, 32, 27
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(seed, T, H, W, torch.float32, torch.float64)
+    out = dsgm.forward(fr, st, p, bg=True, codes=True, ckpt_every=K, acc=dsgm.ACC_F64_IO32)
+    gbg, gst = _grads(seed + 100, T, H, W, torch.float32)
+    r = dsgm.backward(fr, p, out["ckpt"], K, dsgm.ACC_F64_IO32, gbg, gst)
+    torch.cuda.synchronize()
+    ref = _oracle_bwd(seed, T, H, W, torch.float32, torch.float64, p, out["codes"], gbg, gst)
+    G.assert_bit_exact("grad_frames", r["grad_frames"].cpu().numpy().reshape(T, -1),
+                       ref["grad_frames"].astype(np.float32))
+    for i in range(4):
+        G.assert_bit_exact(f"grad_state0[{i}]", r["grad_state0"][i].cpu().numpy().ravel(),
+                           ref["grad_state0"][i].astype(np.float32))
+    px = r["workspace"][: H * W * 8].view(torch.float64).cpu().numpy()
+    G.assert_bit_exact("grad_var_init per pixel", px, ref["grad_var_init_px"])
+
+
+@pytest.mark.slow
+def test_full_size_io32_forward_and_adjoint_sampled():
+    """The largest single instance: 2160 x 3840 pixels x 1344 frames (11.1 G
+    elements), FP32 frames, FP64 state and arithmetic, FP32 bg and gradient
+    arrays, checkpoints every 32 frames, upstream gradients N(0,1), seed 4 --
+    about 200 GB resident.  Sampled pixels: masks and final state bit-identical
+    to the FP64 oracle, bg and gradients equal to its values rounded to FP32."""
+    T, H, W, K, seed = 1344, 2160, 3840, 32, 4
+    acc = dsgm.ACC_F64_IO32
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(seed, T, H, W, torch.float32, torch.float64)
+    st0 = st.clone()
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    bg = torch.empty((T, H, W), dtype=torch.float32, device="cuda")
+    ck = torch.empty(dsgm.dsgm_ckpt_bytes(T, H, W, acc, K), dtype=torch.uint8, device="cuda")
+    dsgm.dsgm_forward(fr, st, p, masks, bg, ck, K, acc=acc)
+    gbg, gst = _grads(seed + 100, T, H, W, torch.float32)
+    r = dsgm.backward(fr, p, ck, K, acc, gbg, gst)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    pix = np.sort(rng.choice(H * W, 256, replace=False))
+    pt = torch.as_tensor(pix, device="cuda")
+    x, s0 = G.host_case(seed, T, H, W, torch.float32, torch.float64, pix=pix)
+    op = G.oracle_params(p)
+    ref = oracle.forward(x, s0, op)
+    G.assert_bit_exact("masks", masks.view(T, -1)[:, pt].cpu().numpy(), ref["masks"])
+    G.assert_bit_exact("bg", bg.view(T, -1)[:, pt].cpu().numpy(), ref["bg"].astype(np.float32))
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k][pix], ref[k])
+    gb = gbg.view(T, -1)[:, pt].double().cpu().numpy()
+    gs = np.stack([g.view(-1)[pt].double().cpu().numpy() for g in gst])
+    rb = oracle.backward(x, s0, op, gb, gs, forced=ref["codes"])
+    G.assert_bit_exact("grad_frames", r["grad_frames"].view(T, -1)[:, pt].cpu().numpy(),
+                       rb["grad_frames"].astype(np.float32))
+    for i in range(4):
+        G.assert_bit_exact(f"grad_state0[{i}]", r["grad_state0"][i].view(-1)[pt].cpu().numpy(),
+                           rb["grad_state0"][i].astype(np.float32))
+    del fr, st, st0, masks, bg, ck, gbg, gst, r

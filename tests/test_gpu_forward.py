@@ -272,3 +272,25 @@ def test_fp32_state_certified_against_oracle(in_dtype):
         assert np.max(np.abs(hs[k][ok] - ref[k][ok]) / np.maximum(ref[k][ok], p.var_init)) <= 1e-5, k
     for k in ("age_a", "age_c"):
         G.assert_bit_exact(k, hs[k][ok], ref[k][ok])
+
+
+@pytest.mark.parametrize("in_dtype", [torch.float32, torch.bfloat16])
+def test_io32_forward_is_fp64_rounded_once(in_dtype):
+    """FP64 state and arithmetic with an FP32 bg array: codes, masks and state
+    bit-identical to the FP64 oracle, bg equal to the oracle's bg rounded to
+    FP32 (round to nearest even)."""
+    T, H, W, seed = 300, 48, 160, 32
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(seed, T, H, W, in_dtype, torch.float64)
+    x, s0 = G.host_case(seed, T, H, W, in_dtype, torch.float64)
+    out = dsgm.forward(fr, st, p, bg=True, codes=True, acc=dsgm.ACC_F64_IO32)
+    assert out["bg"].dtype == torch.float32
+    torch.cuda.synchronize()
+    ref = oracle.forward(x, s0, G.oracle_params(p))
+    G.assert_bit_exact("codes", G.flat(out["codes"]), ref["codes"])
+    G.assert_bit_exact("masks", G.flat(out["masks"]), ref["masks"])
+    G.assert_bit_exact("bg", out["bg"].cpu().numpy().reshape(T, -1),
+                       ref["bg"].astype(np.float32))
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k], ref[k])
