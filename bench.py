@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
 """Throughput of the DSGM hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs main,mixed,adjoint,batched]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--legs main,mixed,video,attainable,adjoint,batched,largest]
                     [--no-cpu-baseline]
 
 Main workload (the `value`): the plain method in FP64, one instance of
@@ -16,10 +17,16 @@ Secondary legs, reported under "legs" (same timing method):
   mixed    BF16 frames (8-bit grid) with FP32 state vs the FP64 path on the same
            frames: throughput of both, and how far the FP32 results are from the
            FP64 ones (which the parity tests prove bit-identical to the oracle)
+  video    the same size on a structured video (static background, exposure step,
+           moving rectangles, 8-bit levels) from a state initialised from frame 0:
+           FP64 and BF16/FP32 throughput on a realistic decision mix
+  attainable  the same bytes as the forward and backward kernels moved by kernels
+           with no model arithmetic: the attainable HBM rate of each access pattern
   adjoint  FP32 frames and state, bg on, checkpoints every 32 frames, upstream
            gradients ~N(0,1) (seed 2): forward and dsgm_backward throughput
   batched  512 instances of log-uniform size (seed 3), BF16 frames, FP32 state,
-           one graph-captured persistent launch per step
+           one graph-captured persistent launch per step, against the plain FP64
+           form (FP64 frames of the same values, FP64 state) on the same instances
   largest  one 2160x3840x1344 instance (~200 GB resident), FP32 frames, FP64
            state and arithmetic, FP32 bg and gradients: forward and backward
 
@@ -174,6 +181,66 @@ def leg_mixed(args, dsgm, sdev, torch):
     return out
 
 
+def leg_video(args, dsgm, sdev, torch):
+    """The structured video (static background, exposure step at frame 250,
+    six moving rectangles, ~3-level noise, 8-bit levels), 1920x2560x500, seed 1,
+    state initialised from frame 0 before the first step; FP64 and BF16/FP32."""
+    T, H, W, seed = 500, 1920, 2560, 1
+    p = dsgm.dsgm_params_default(2.0)
+    stream = torch.cuda.current_stream()
+    elems, px = T * H * W, H * W
+    steps = max(3, args.steps // 2)
+    out = {"workload": "structured video 1920x2560x500 seed 1, masks only, state from frame 0"}
+    for name, in_dt, acc_dt, in_b, st_b in (("fp64", torch.float64, torch.float64, 8, 68),
+                                             ("bf16_fp32", torch.bfloat16, torch.float32, 2, 36)):
+        fr = sdev.video(seed, T, H, W, in_dt)
+        st = dsgm.State.empty(H, W, acc_dt)
+        dsgm.dsgm_state_init_from_frame(fr[0], st, p)
+        masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+        ms, kk = timed(lambda: dsgm.dsgm_forward(fr, st, p, masks), steps, 1, stream)
+        out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                     "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)))}
+        del fr, st, masks
+        torch.cuda.empty_cache()
+    return out
+
+
+def leg_attainable(args, dsgm, sdev, torch):
+    """Attainable HBM rate of each kernel's access pattern: kernels that move the
+    same bytes in the same order, widths and cache hints as the forward and
+    backward kernels but do no model arithmetic (synth/probe.hip), at the size
+    of the main and adjoint workloads.  The real kernels' rates are compared
+    with these as well as with the published peak."""
+    T, H, W = 500, 1920, 2560
+    npx, elems = H * W, T * H * W
+    stream = torch.cuda.current_stream()
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = {}
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    for name, dt, P in (("forward_f64_frames_p2", torch.float64, 2),
+                        ("forward_f32_frames_p2", torch.float32, 2),
+                        ("forward_bf16_frames_p4", torch.bfloat16, 4)):
+        fr = torch.zeros((T, H, W), dtype=dt, device="cuda")
+        ms, kk = timed(lambda: sdev.probe_forward(fr, P, masks, sink), 5, 2, stream)
+        k = float(sum(kk) / len(kk))
+        out[name] = {"bytes_per_element": fr.element_size() + 1, "kernel_ms": round(k, 4),
+                     "GB_per_s": round(elems * (fr.element_size() + 1) / (k * 1e-3) / 1e9, 1)}
+        del fr
+        torch.cuda.empty_cache()
+    del masks
+    for name, dt in (("backward_f32", torch.float32), ("backward_f64", torch.float64)):
+        x = torch.zeros((T, H, W), dtype=dt, device="cuda")
+        g = torch.zeros_like(x)
+        gx = torch.empty_like(x)
+        ms, kk = timed(lambda: sdev.probe_backward(x, g, gx), 5, 2, stream)
+        k = float(sum(kk) / len(kk))
+        out[name] = {"bytes_per_element": 3 * x.element_size(), "kernel_ms": round(k, 4),
+                     "GB_per_s": round(elems * 3 * x.element_size() / (k * 1e-3) / 1e9, 1)}
+        del x, g, gx
+        torch.cuda.empty_cache()
+    return out
+
+
 def leg_adjoint(args, dsgm, sdev, torch):
     T, H, W, K, seed = 500, 1920, 2560, 32, 2
     p = dsgm.dsgm_params_default(2.0)
@@ -283,16 +350,38 @@ def batch_seed(i: int) -> int:
     return 3000 + i
 
 
+def _batch_items(shapes, idx, dsgm, sdev, torch, frames_dtype, state_dtype, st0):
+    """Instances `idx` of the batch: BF16-grid frames stored as `frames_dtype`
+    (exact upcast), the FP32 initial state `st0[i]` stored as `state_dtype`."""
+    items = []
+    for i in idx:
+        T, H, W = shapes[i]
+        fr = sdev.frames(batch_seed(i), T, H, W, torch.bfloat16)
+        if frames_dtype != torch.bfloat16:
+            fr = fr.to(frames_dtype)
+        s = st0[i]
+        st = dsgm.State(s.mean_a.to(state_dtype), s.var_a.to(state_dtype), s.mean_c.to(state_dtype),
+                        s.var_c.to(state_dtype), s.age_a.clone(), s.age_c.clone())
+        items.append((fr, st, torch.empty((T, H, W), dtype=torch.uint8, device="cuda"), None))
+    return items
+
+
 def leg_batched(args, dsgm, sdev, torch):
+    """The mixed-precision batched form (BF16 frames, FP32 state, one graph-
+    captured persistent launch) against the plain FP64 form (FP64 frames holding
+    the same values, FP64 state from the same initial values) on the same 512
+    instances.  The FP64 form does not fit in HBM at once (481 GB of frames), so
+    it runs as consecutive batched launches over chunks of the instance list and
+    its time is the sum of the chunks'.  Accuracy: the masks of one pass from
+    the common initial state, mixed vs FP64."""
     shapes = batch_shapes()
     p = dsgm.dsgm_params_default(2.0)
-    items = []
-    for i, (T, H, W) in enumerate(shapes):
-        fr = sdev.frames(batch_seed(i), T, H, W, torch.bfloat16)
-        st = dsgm.State(*sdev.state(batch_seed(i), H, W, torch.float32))
-        items.append((fr, st, torch.empty((T, H, W), dtype=torch.uint8, device="cuda"), None))
-    batch = dsgm.Batch(items)
     stream = torch.cuda.current_stream()
+    st0 = [dsgm.State(*sdev.state(batch_seed(i), H, W, torch.float32)) for i, (T, H, W) in
+           enumerate(shapes)]
+    items = _batch_items(shapes, range(len(shapes)), dsgm, sdev, torch, torch.bfloat16,
+                         torch.float32, st0)
+    batch = dsgm.Batch(items)
     batch.run(p)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -306,14 +395,61 @@ def leg_batched(args, dsgm, sdev, torch):
     elems = batch.plan.total_elements
     px = sum(H * W for _, H, W in shapes)
     alg = elems * 3 + px * 36
-    out = {"workload": "512 instances, log-uniform 1x..256x of 320x240x32, bf16 frames, fp32 state, "
-                       "masks only, seed 3",
-           "instances": len(shapes), "total_elements": int(elems), "work_items": int(batch.plan.n_items),
-           "persistent_workgroups": int(batch.plan.grid),
-           "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-           "roofline": roof(alg, float(sum(kk) / len(kk)))}
+    n_items, grid = int(batch.plan.n_items), int(batch.plan.grid)
+    # one pass from the initial state for the accuracy comparison
+    for (_, st, _, _), s0 in zip(items, st0):
+        for a, b in zip(st.planes(), s0.planes()):
+            a.copy_(b)
+    batch.run(p)
+    torch.cuda.synchronize()
+    masks_mixed = [m for _, _, m, _ in items]
     del items, batch, g
     torch.cuda.empty_cache()
+
+    # the FP64 form, chunked to fit
+    chunks, cur, cur_bytes = [], [], 0
+    for i, (T, H, W) in enumerate(shapes):
+        b = T * H * W * 8
+        if cur and cur_bytes + b > 130e9:
+            chunks.append(cur)
+            cur, cur_bytes = [], 0
+        cur.append(i)
+        cur_bytes += b
+    chunks.append(cur)
+    ms64 = 0.0
+    k64 = []
+    diff_elems = 0
+    diff_px = 0
+    for idx in chunks:
+        it = _batch_items(shapes, idx, dsgm, sdev, torch, torch.float64, torch.float64, st0)
+        b64 = dsgm.Batch(it)
+        b64.run(p)
+        torch.cuda.synchronize()
+        for i, (_, _, m, _) in zip(idx, it):
+            d = m != masks_mixed[i]
+            diff_elems += int(d.sum().item())
+            diff_px += int(d.any(dim=0).sum().item())
+        m_chunk, k_chunk = timed(lambda: b64.run(p), steps, 1, stream)
+        ms64 += m_chunk
+        k64.append(float(sum(k_chunk) / len(k_chunk)))
+        del it, b64
+        torch.cuda.empty_cache()
+    del masks_mixed, st0
+    torch.cuda.empty_cache()
+    out = {"workload": "512 instances, log-uniform 1x..256x of 320x240x32, bf16 frames, fp32 state, "
+                       "masks only, seed 3",
+           "instances": len(shapes), "total_elements": int(elems), "work_items": n_items,
+           "persistent_workgroups": grid,
+           "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+           "roofline": roof(alg, float(sum(kk) / len(kk))),
+           "fp64_form": {"workload": "the same 512 instances, fp64 frames (same values) and fp64 "
+                                     "state, batched launches over %d chunks" % len(chunks),
+                         "elements_per_s": round(elems / (ms64 * 1e-3), 1),
+                         "ms_per_step": round(ms64, 4),
+                         "roofline": roof(elems * 9 + px * 68, sum(k64))},
+           "speedup_mixed_over_fp64": round(ms64 / ms, 3),
+           "error_vs_fp64": {"mask_elements_differing_frac": diff_elems / elems,
+                             "pixels_with_any_mask_difference_frac": diff_px / px}}
     return out
 
 
@@ -322,7 +458,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="main,mixed,adjoint,batched,largest")
+    ap.add_argument("--legs", default="main,mixed,video,attainable,adjoint,batched,largest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
@@ -379,6 +515,10 @@ def main():
     out_legs = {}
     if "mixed" in legs:
         out_legs["mixed"] = leg_mixed(args, dsgm, sdev, torch)
+    if "video" in legs:
+        out_legs["video"] = leg_video(args, dsgm, sdev, torch)
+    if "attainable" in legs:
+        out_legs["attainable"] = leg_attainable(args, dsgm, sdev, torch)
     if "adjoint" in legs:
         out_legs["adjoint"] = leg_adjoint(args, dsgm, sdev, torch)
     if "batched" in legs:

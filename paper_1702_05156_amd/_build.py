@@ -22,7 +22,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdsgm.so")
-SYNTH_SRC = os.path.join(ROOT, "synth", "synth.hip")
+SYNTH_SRCS = [os.path.join(ROOT, "synth", "synth.hip"), os.path.join(ROOT, "synth", "probe.hip")]
 SYNTH_LIB = os.path.join(ROOT, "synth", "libsynth.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -58,14 +58,13 @@ def build(verbose: bool = False, jobs: int | None = None) -> list[str]:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = [ex.submit(_compile, s, os.path.join(BUILD, os.path.basename(s) + ".o"),
                           [INCLUDE, CSRC], verbose) for s in srcs]
-        futs.append(ex.submit(_compile, SYNTH_SRC, os.path.join(BUILD, "synth.hip.o"),
-                              [os.path.join(ROOT, "synth")], verbose))
-        for f in futs:
-            objs.append(f.result())
-    synth_obj = objs.pop()
+        sfuts = [ex.submit(_compile, s, os.path.join(BUILD, "synth_" + os.path.basename(s) + ".o"),
+                           [os.path.join(ROOT, "synth")], verbose) for s in SYNTH_SRCS]
+        objs = [f.result() for f in futs]
+        synth_objs = [f.result() for f in sfuts]
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-o", LIB + ".tmp"] + objs, verbose)
     os.replace(LIB + ".tmp", LIB)
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-o", SYNTH_LIB + ".tmp", synth_obj], verbose)
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-o", SYNTH_LIB + ".tmp"] + synth_objs, verbose)
     os.replace(SYNTH_LIB + ".tmp", SYNTH_LIB)
     return [LIB, SYNTH_LIB]
 

@@ -5,7 +5,7 @@
 // written branch-free for 64-wide wavefronts:
 //
 //   match tests   hitA = (x-mA)^2 < ts*max(vA, vf); hitC = (x-mC)^2 < ts*max(vC, vf)
-//                 (evaluated as two comparisons, see step())
+//                 (evaluated as two comparisons, see step_core())
 //                 (C only counts when A failed: the table index below gives A priority)
 //   update        the matched model (A if hitA, else C) is blended with x using the
 //                 weights of its age (Sec. 2.2): m' = u*m + w*x, V = (m'-x)^2,
@@ -16,8 +16,8 @@
 //                 0*m + 1*x = x, (x-x)^2 = 0, 0*v + 1*0 + var_init = var_init, all
 //                 exact in IEEE arithmetic, so no extra select is needed.
 //   exchange      if hitA the result goes to A, else to C
-//   swap          C older than A: A = C, C = (x, var_init, 1) (rare, so a branch
-//                 that the whole wavefront skips when no lane swaps)
+//   swap          C older than A: A = C, C = (x, var_init, 1) (rare: a branch
+//                 that the whole wavefront skips when no lane swaps, any_lane())
 //   mask          background iff (mA-x)^2 <= td*max(mf, ref), ref = vA or x
 //
 // With Acc = double every product and sum is rounded on its own (the library is
@@ -100,12 +100,17 @@ struct StepRecord {
   bool hitA, hitC, swap, fg;
 };
 
-// One frame of one pixel (state updated in place).  PRINTED selects the mask
-// rule: reference = the intensity (as printed) or var_A.
-template <typename Acc, bool PRINTED>
-__device__ __forceinline__ StepRecord<Acc> step_rec(Model<Acc>& s, const Acc x,
-                                                    const StepConsts<Acc>& k,
-                                                    const TableEntry<Acc>* __restrict__ tbl) {
+// True when the condition holds in any active lane of the wavefront.  Used to
+// skip the rarely taken exchange as a whole: inside the branch every lane still
+// applies it under its own condition, so results do not depend on the wavefront.
+__device__ __forceinline__ bool any_lane(bool b) { return __builtin_amdgcn_ballot_w64(b) != 0; }
+
+// Match tests, update of the matched model and the exchange decision (not yet
+// applied) for one frame of one pixel.  r.fg is left unset.
+template <typename Acc>
+__device__ __forceinline__ StepRecord<Acc> step_core(Model<Acc>& s, const Acc x,
+                                                     const StepConsts<Acc>& k,
+                                                     const TableEntry<Acc>* __restrict__ tbl) {
   // q < theta*max(v, f)  <=>  q < theta*v  or  q < theta*f  for theta >= 0:
   // rounding is monotone, so round(theta*max(v,f)) = max(round(theta*v),
   // round(theta*f)); the floor products are per-launch constants.
@@ -135,41 +140,54 @@ __device__ __forceinline__ StepRecord<Acc> step_rec(Model<Acc>& s, const Acc x,
   s.vC = hitA ? s.vC : vn;
   s.aC = hitA ? s.aC : an;
 
-  const bool swap = s.aC > s.aA;
-  if (swap) {
-    s.mA = s.mC;
-    s.vA = s.vC;
-    s.aA = s.aC;
-    s.mC = x;
-    s.vC = k.var_init;
-    s.aC = 1;
-  }
-
-  const Acc dd = s.mA - x;
-  const Acc qd = dd * dd;
-  const Acc ref = PRINTED ? x : s.vA;
-  const bool fg = !((qd <= k.theta_d * ref) | (qd <= k.td_mf));
   StepRecord<Acc> r;
   r.d = d;
   r.idx = idx;
   r.hitA = hitA;
   r.hitC = hitC && !hitA;
-  r.swap = swap;
-  r.fg = fg;
+  r.swap = s.aC > s.aA;
+  r.fg = false;
   return r;
 }
 
-// One frame of one pixel.  Returns the foreground flag; writes the decision
-// code to *code when CODES.
-template <typename Acc, bool CODES, bool PRINTED>
-__device__ __forceinline__ bool step(Model<Acc>& s, const Acc x, const StepConsts<Acc>& k,
-                                     const TableEntry<Acc>* __restrict__ tbl, unsigned* code) {
-  const StepRecord<Acc> r = step_rec<Acc, PRINTED>(s, x, k, tbl);
-  if (CODES) {
-    *code = (r.hitA ? CODE_HIT_A : (r.hitC ? CODE_HIT_C : CODE_RESET)) |
-            (r.swap ? CODE_SWAP : 0u) | (r.fg ? CODE_FG : 0u);
-  }
-  return r.fg;
+// The exchange: C older than A makes C the new A and resets C to (x, var_init, 1).
+template <typename Acc>
+__device__ __forceinline__ void apply_swap(Model<Acc>& s, const Acc x, const StepConsts<Acc>& k,
+                                           const bool swap) {
+  s.mA = swap ? s.mC : s.mA;
+  s.vA = swap ? s.vC : s.vA;
+  s.aA = swap ? s.aC : s.aA;
+  s.mC = swap ? x : s.mC;
+  s.vC = swap ? k.var_init : s.vC;
+  s.aC = swap ? 1 : s.aC;
+}
+
+// The mask of the step (on the state after the exchange).  PRINTED selects the
+// rule's reference: the intensity (as printed) or var_A.
+template <typename Acc, bool PRINTED>
+__device__ __forceinline__ bool fg_of(const Model<Acc>& s, const Acc x, const StepConsts<Acc>& k) {
+  const Acc dd = s.mA - x;
+  const Acc qd = dd * dd;
+  const Acc ref = PRINTED ? x : s.vA;
+  return !((qd <= k.theta_d * ref) | (qd <= k.td_mf));
+}
+
+// One whole frame of one pixel (state updated in place).
+template <typename Acc, bool PRINTED>
+__device__ __forceinline__ StepRecord<Acc> step_rec(Model<Acc>& s, const Acc x,
+                                                    const StepConsts<Acc>& k,
+                                                    const TableEntry<Acc>* __restrict__ tbl) {
+  StepRecord<Acc> r = step_core<Acc>(s, x, k, tbl);
+  if (any_lane(r.swap)) apply_swap<Acc>(s, x, k, r.swap);
+  r.fg = fg_of<Acc, PRINTED>(s, x, k);
+  return r;
+}
+
+// The decision code of a step (CODE_* bits).
+template <typename Acc>
+__device__ __forceinline__ unsigned code_of(const StepRecord<Acc>& r) {
+  return (r.hitA ? CODE_HIT_A : (r.hitC ? CODE_HIT_C : CODE_RESET)) | (r.swap ? CODE_SWAP : 0u) |
+         (r.fg ? CODE_FG : 0u);
 }
 
 // Adjoint of one step, decisions fixed (the chain rule through step_rec):
@@ -192,13 +210,13 @@ __device__ __forceinline__ Acc reverse_step(Adjoint<Acc>& g, const Acc gbg, cons
                                             const TableEntry<Acc>* __restrict__ tbl) {
   if (HAS_GBG) g.gmA = g.gmA + gbg;
   Acc gx = Acc(0);
-  if (swap) {
-    gx = gx + g.gmC;
-    g.gvi += double(g.gvC);
-    g.gmC = g.gmA;
-    g.gvC = g.gvA;
-    g.gmA = Acc(0);
-    g.gvA = Acc(0);
+  if (any_lane(swap)) {
+    gx = swap ? gx + g.gmC : gx;
+    g.gvi = swap ? g.gvi + double(g.gvC) : g.gvi;
+    g.gmC = swap ? g.gmA : g.gmC;
+    g.gvC = swap ? g.gvA : g.gvC;
+    g.gmA = swap ? Acc(0) : g.gmA;
+    g.gvA = swap ? Acc(0) : g.gvA;
   }
   const TableEntry<Acc> e = tbl[idx];
   const Acc gm = hitA ? g.gmA : g.gmC;

@@ -181,13 +181,26 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
     Vec<uint8_t, P> mk;
     Vec<Io, P> bgv;
     Vec<uint8_t, P> cd;
+    // the P pixels' exchanges share one wavefront-uniform branch
+    Acc xs[P];
+    StepRecord<Acc> r[P];
+    bool any = false;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      unsigned c = 0;
-      const bool fg = step<Acc, CODES, PRINTED>(s[q], to_acc<In, Acc>(xin.v[q]), k, tbl, &c);
-      mk.v[q] = fg ? uint8_t(255) : uint8_t(0);
+      xs[q] = to_acc<In, Acc>(xin.v[q]);
+      r[q] = step_core<Acc>(s[q], xs[q], k, tbl);
+      any |= r[q].swap;
+    }
+    if (any_lane(any)) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) apply_swap<Acc>(s[q], xs[q], k, r[q].swap);
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      r[q].fg = fg_of<Acc, PRINTED>(s[q], xs[q], k);
+      mk.v[q] = r[q].fg ? uint8_t(255) : uint8_t(0);
       if (BG) bgv.v[q] = Io(s[q].mA);  // rounded once when Io is narrower
-      if (CODES) cd.v[q] = uint8_t(c);
+      if (CODES) cd.v[q] = uint8_t(code_of<Acc>(r[q]));
     }
     const int64_t o = t * fs;
     st_stream<uint8_t, P>(reinterpret_cast<uint8_t*>(j.masks + o + j.foff), mk);

@@ -26,6 +26,22 @@ Value maps (all exact, no rounding anywhere):
   normal       : Irwin-Hall sum of 12 16-bit uniforms from draws 3i, 3i+1, 3i+2
                  (four 16-bit chunks each, low chunk first):
                  (sum_chunks - 393210) * 2**-16, mean 0, variance ~1, exact in f32.
+  below(k, n)  : ((k >> 32) * n) >> 32, an integer in [0, n)
+
+Structured video (``video``): 8-bit-like levels q in [-128, 127], value q/128
+(exact in f64, f32 and bf16), all in integer arithmetic:
+  background  bq(p) = below(draw(seed, 11, p), 161) - 80, static per pixel
+  lighting    + 4 levels from frame T//2 on (a global exposure step)
+  objects     6 rectangles, parameters from draws 8r..8r+6 of stream 13:
+              top0 = below(k0, H), left0 = below(k1, W),
+              height = H//16 + below(k2, H//8 + 1), width = W//16 + below(k3, W//8 + 1),
+              vy = below(k4, 7) - 3, vx = below(k5, 9) - 4, level = below(k6, 256) - 128;
+              at frame t the rectangle starts at ((top0 + vy*t) mod H, (left0 + vx*t) mod W)
+              and wraps around the frame edges; a later rectangle covers an earlier one
+  noise       n = floor((3 * (S - 393210) + 2**15) / 2**16), S the Irwin-Hall sum of
+              stream 12 at the element's logical index (mean 0, standard deviation ~3 levels)
+  value       clamp(level + n, -128, 127) / 128 with level = the covering rectangle's
+              level, else bq + lighting.
 
 The logical index of element (t, h, w) of a T x H x W array is t*H*W + h*W + w,
 whatever the strides of the buffer it is stored in.
@@ -49,6 +65,12 @@ STREAM_AGE_C = 6
 STREAM_GRAD_BG = 7
 STREAM_GRAD_STATE = 8
 STREAM_DIRECTION = 9
+STREAM_BATCH_SIZES = 10
+STREAM_VIDEO_BG = 11
+STREAM_VIDEO_NOISE = 12
+STREAM_VIDEO_RECTS = 13
+VIDEO_RECTS = 6
+VIDEO_LIGHT_STEP = 4
 
 DTYPES = ("f64", "f32", "bf16")
 
@@ -102,6 +124,17 @@ def ages(seed: int, stream: int, index, age_max: int) -> np.ndarray:
 
 def normal(seed: int, stream: int, index) -> np.ndarray:
     """Approximately N(0,1): Irwin-Hall sum of 12 16-bit uniforms (exact in f32)."""
+    return (irwin_hall_sum(seed, stream, index) - 393210).astype(np.float64) * 2.0 ** -16
+
+
+def below(k: np.ndarray, n: int) -> np.ndarray:
+    """Map 64-bit draws to integers in [0, n) (n < 2**32), as int64."""
+    with np.errstate(over="ignore"):
+        return ((np.asarray(k, dtype=np.uint64) >> np.uint64(32)) * np.uint64(n) >> np.uint64(32)).astype(np.int64)
+
+
+def irwin_hall_sum(seed: int, stream: int, index) -> np.ndarray:
+    """The integer Irwin-Hall sum S of ``normal`` (so normal = (S - 393210) * 2**-16)."""
     idx = np.asarray(index, dtype=np.uint64)
     total = np.zeros(idx.shape, dtype=np.int64)
     mask16 = np.uint64(0xFFFF)
@@ -110,7 +143,46 @@ def normal(seed: int, stream: int, index) -> np.ndarray:
             k = draws(seed, stream, idx * np.uint64(3) + np.uint64(j))
         for c in range(4):
             total += ((k >> np.uint64(16 * c)) & mask16).astype(np.int64)
-    return (total - 393210).astype(np.float64) * 2.0 ** -16
+    return total
+
+
+def video_rects(seed: int, H: int, W: int) -> np.ndarray:
+    """The six rectangles of ``video``: rows (top0, left0, height, width, vy, vx, level)."""
+    k = draws(seed, STREAM_VIDEO_RECTS, np.arange(8 * VIDEO_RECTS, dtype=np.uint64)).reshape(VIDEO_RECTS, 8)
+    out = np.empty((VIDEO_RECTS, 7), dtype=np.int64)
+    out[:, 0] = below(k[:, 0], H)
+    out[:, 1] = below(k[:, 1], W)
+    out[:, 2] = H // 16 + below(k[:, 2], H // 8 + 1)
+    out[:, 3] = W // 16 + below(k[:, 3], W // 8 + 1)
+    out[:, 4] = below(k[:, 4], 7) - 3
+    out[:, 5] = below(k[:, 5], 9) - 4
+    out[:, 6] = below(k[:, 6], 256) - 128
+    return out
+
+
+def video_levels(seed: int, T: int, H: int, W: int, t=None, pix=None) -> np.ndarray:
+    """Integer levels q in [-128, 127] of the structured video, shape (len(t), len(pix))."""
+    t = np.arange(T, dtype=np.int64) if t is None else np.asarray(t, dtype=np.int64)
+    pix = np.arange(H * W, dtype=np.int64) if pix is None else np.asarray(pix, dtype=np.int64)
+    h = (pix // W)[None, :]
+    w = (pix % W)[None, :]
+    tt = t[:, None]
+    level = (below(draws(seed, STREAM_VIDEO_BG, pix.astype(np.uint64)), 161) - 80)[None, :] \
+        + np.where(tt >= T // 2, VIDEO_LIGHT_STEP, 0)
+    level = np.broadcast_to(level, (len(t), len(pix))).copy()
+    for top0, left0, rh, rw, vy, vx, lq in video_rects(seed, H, W):
+        top = (top0 + vy * tt) % H
+        left = (left0 + vx * tt) % W
+        inside = ((h - top) % H < rh) & ((w - left) % W < rw)
+        level = np.where(inside, lq, level)
+    idx = (tt.astype(np.uint64) * np.uint64(H * W) + pix.astype(np.uint64)[None, :])
+    noise = ((irwin_hall_sum(seed, STREAM_VIDEO_NOISE, idx) - 393210) * 3 + 32768) >> 16
+    return np.clip(level + noise, -128, 127)
+
+
+def video(seed: int, T: int, H: int, W: int, t=None, pix=None) -> np.ndarray:
+    """Structured video frames as float64 values q/128, shape (len(t), len(pix))."""
+    return video_levels(seed, T, H, W, t, pix).astype(np.float64) / 128.0
 
 
 # ---------------------------------------------------------------- workloads

@@ -30,6 +30,9 @@ def lib():
         vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         _lib.synth_fill.argtypes = [vp, i32, i32, i64, i64, i64, i64, i64, u64, u64, vp]
         _lib.synth_ages.argtypes = [vp, i64, i32, u64, u64, vp]
+        _lib.synth_video.argtypes = [vp, i32, i64, i64, i64, i64, i64, u64, vp]
+        _lib.synth_probe_forward.argtypes = [vp, i32, i32, vp, vp, i64, i64, vp]
+        _lib.synth_probe_backward.argtypes = [vp, vp, vp, i32, i64, i64, vp]
     return _lib
 
 
@@ -64,6 +67,17 @@ def frames(seed: int, T: int, H: int, W: int, dtype=torch.float64, device="cuda"
     return fill(torch.empty((T, H, W), dtype=dtype, device=device), seed, STREAM_FRAMES)
 
 
+def video(seed: int, T: int, H: int, W: int, dtype=torch.float64, device="cuda") -> torch.Tensor:
+    """The structured video of ``synth.video`` (values q/128, exact in every dtype)."""
+    v = torch.empty((T, H, W), dtype=dtype, device=device)
+    fs, rs, _ = v.stride()
+    rc = lib().synth_video(ctypes.c_void_p(v.data_ptr()), _DT[dtype], T, H, W, rs if H > 1 else W,
+                           fs if T > 1 else H * max(rs, W), seed, _stream())
+    if rc != 0:
+        raise RuntimeError(f"synth_video failed ({rc})")
+    return v
+
+
 def state(seed: int, H: int, W: int, dtype=torch.float64, age_max: int = 30, device="cuda"):
     """The random mid-run state of ``synth.state`` as a tuple of six device tensors
     (mean_a, var_a, mean_c, var_c, age_a, age_c)."""
@@ -80,3 +94,31 @@ def grad_bg(seed: int, T: int, H: int, W: int, dtype=torch.float64, device="cuda
 def grad_state(seed: int, H: int, W: int, dtype=torch.float64, device="cuda") -> torch.Tensor:
     """(4, H, W): upstream gradient of the final (mean_a, var_a, mean_c, var_c)."""
     return fill(torch.empty((4, H, W), dtype=dtype, device=device), seed, STREAM_GRAD_STATE, NORMAL)
+
+
+def probe_forward(frames: torch.Tensor, pixels_per_lane: int, masks: torch.Tensor,
+                  sink: torch.Tensor) -> None:
+    """The forward kernel's memory traffic with no model arithmetic (dense T x H x W)."""
+    T = frames.shape[0]
+    npx = frames[0].numel()
+    assert frames.is_contiguous() and masks.is_contiguous() and masks.numel() == T * npx
+    assert masks.dtype == torch.uint8 and sink.numel() >= 1
+    rc = lib().synth_probe_forward(ctypes.c_void_p(frames.data_ptr()), frames.element_size(),
+                                   pixels_per_lane, ctypes.c_void_p(masks.data_ptr()),
+                                   ctypes.c_void_p(sink.data_ptr()), T, npx, _stream())
+    if rc != 0:
+        raise RuntimeError(f"synth_probe_forward failed ({rc})")
+
+
+def probe_backward(x: torch.Tensor, g: torch.Tensor, gx: torch.Tensor) -> None:
+    """The backward kernel's frame-sized traffic (x, g in; gx out) with no arithmetic."""
+    T = x.shape[0]
+    npx = x[0].numel()
+    for t in (g, gx):
+        assert t.is_contiguous() and t.shape == x.shape and t.dtype == x.dtype
+    assert x.is_contiguous()
+    rc = lib().synth_probe_backward(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                    ctypes.c_void_p(gx.data_ptr()), x.element_size(), T, npx,
+                                    _stream())
+    if rc != 0:
+        raise RuntimeError(f"synth_probe_backward failed ({rc})")

@@ -1,0 +1,101 @@
+"""GPU parity on the structured video input (static background, a global
+exposure step, moving rectangles, ~3-level noise; values q/128 on an 8-bit
+grid) from a state initialised from frame 0.  Unlike the i.i.d. frames, the
+A match dominates early and the swap path fires while the models are young.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from synth import device as sdev
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+
+
+def _init_state_host(x0, p):
+    n = x0.size
+    return {"mean_a": x0.copy(), "mean_c": x0.copy(), "var_a": np.full(n, p.var_init),
+            "var_c": np.full(n, p.var_init), "age_a": np.ones(n, np.int32),
+            "age_c": np.ones(n, np.int32)}
+
+
+def _init_state_dev(fr, acc_dtype, p):
+    H, W = fr.shape[1:]
+    st = dsgm.State.empty(H, W, acc_dtype)
+    dsgm.dsgm_state_init_from_frame(fr[0], st, p)
+    return st
+
+
+def test_video_twin_bit_identical():
+    T, H, W = 9, 23, 37
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        d = sdev.video(8, T, H, W, dt)
+        G.assert_bit_exact(f"video {dt}", G.flat(d), synth.video(8, T, H, W))
+
+
+@pytest.mark.parametrize("T,H,W", [(300, 48, 64), (61, 13, 37)])
+def test_video_f64_bit_exact(T, H, W):
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.video(9, T, H, W, torch.float64)
+    st = _init_state_dev(fr, torch.float64, p)
+    out = dsgm.forward(fr, st, p, bg=True, codes=True)
+    torch.cuda.synchronize()
+    x = synth.video(9, T, H, W)
+    ref = oracle.forward(x, _init_state_host(x[0], p), G.oracle_params(p))
+    G.assert_bit_exact("codes", G.flat(out["codes"]), ref["codes"])
+    G.assert_bit_exact("masks", G.flat(out["masks"]), ref["masks"])
+    G.assert_bit_exact("bg", G.flat(out["bg"]), ref["bg"])
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k], ref[k])
+    # the structure this input is for: A matches dominate the first frames, and
+    # swaps occur (the forward's wavefront-skipped exchange is exercised)
+    c = ref["codes"]
+    assert np.mean((c[: T // 4] & 1) != 0) > 0.6
+    assert np.any((c & 8) != 0)
+
+
+def test_video_bf16_fp32_certified():
+    from tests.test_gpu_forward import _certify_fp32
+    T, H, W = 300, 64, 96
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.video(10, T, H, W, torch.bfloat16)
+    st = _init_state_dev(fr, torch.float32, p)
+    out = dsgm.forward(fr, st, p, bg=True, codes=True)
+    torch.cuda.synchronize()
+    x = synth.video(10, T, H, W)
+    s0 = _init_state_host(x[0], p)
+    s0["var_a"] = s0["var_c"] = np.full(H * W, float(np.float32(p.var_init)))
+    ref = oracle.forward(x, s0, G.oracle_params(p), margins=True)
+    div = _certify_fp32(G.flat(out["codes"]), ref)
+    assert div.mean() <= 1e-3, div.mean()
+    ok = ~div
+    assert np.max(np.abs(G.flat(out["bg"])[:, ok] - ref["bg"][:, ok])) <= 1e-5
+
+
+def test_video_f64_adjoint_bit_exact():
+    T, H, W, K = 120, 16, 40, 16
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.video(11, T, H, W, torch.float64)
+    st = _init_state_dev(fr, torch.float64, p)
+    out = dsgm.forward(fr, st, p, bg=True, codes=True, ckpt_every=K)
+    gbg = sdev.grad_bg(111, T, H, W, torch.float64)
+    gst = sdev.grad_state(111, H, W, torch.float64)
+    gst = tuple(gst[i].contiguous() for i in range(4))
+    r = dsgm.backward(fr, p, out["ckpt"], K, dsgm.ACC_F64, gbg, gst)
+    torch.cuda.synchronize()
+    x = synth.video(11, T, H, W)
+    gs = np.stack([g.cpu().numpy().ravel() for g in gst])
+    ref = oracle.backward(x, _init_state_host(x[0], p), G.oracle_params(p), G.flat(gbg), gs,
+                          forced=G.flat(out["codes"]).astype(np.uint8))
+    G.assert_bit_exact("grad_frames", G.flat(r["grad_frames"]), ref["grad_frames"])
+    for i, name in enumerate(("mean_a", "var_a", "mean_c", "var_c")):
+        G.assert_bit_exact(f"grad_{name}0", r["grad_state0"][i].cpu().numpy().ravel(),
+                           ref["grad_state0"][i])
+    assert float(r["grad_var_init"].item()) == pytest.approx(ref["grad_var_init"], rel=1e-15,
+                                                               abs=1e-300)

@@ -54,3 +54,34 @@ def test_logical_index_layout():
     part = synth.frames(0, T, H, W, "f64", t=[2], pix=[7, 19])
     assert full.shape == (T, H * W)
     assert np.array_equal(part[0], full[2, [7, 19]])
+
+
+def test_video_levels_and_slices():
+    """The structured video: 8-bit levels, consistent when evaluated on a
+    subset of frames and pixels, noise centred with ~3 levels of spread."""
+    T, H, W = 20, 16, 24
+    q = synth.video_levels(4, T, H, W)
+    assert q.min() >= -128 and q.max() <= 127
+    assert np.array_equal(synth.video(4, T, H, W), q / 128.0)
+    t = np.array([0, 7, 19])
+    pix = np.array([0, 5, 100, H * W - 1])
+    assert np.array_equal(synth.video_levels(4, T, H, W, t=t, pix=pix), q[t][:, pix])
+    s = synth.irwin_hall_sum(4, synth.STREAM_VIDEO_NOISE, np.arange(200000))
+    n = ((s - 393210) * 3 + 32768) >> 16
+    assert abs(n.mean()) < 0.05 and 2.9 < n.std() < 3.1
+    r = synth.video_rects(4, H, W)
+    assert r.shape == (synth.VIDEO_RECTS, 7)
+    assert np.all((r[:, 2] >= H // 16) & (r[:, 2] <= H // 16 + H // 8))
+    assert np.all((r[:, 4] >= -3) & (r[:, 4] <= 3) & (r[:, 5] >= -4) & (r[:, 5] <= 4))
+
+
+def test_video_rectangle_moves():
+    """A pixel covered by the last rectangle at frame t shows that rectangle's
+    level up to the noise, at the position its velocity gives."""
+    T, H, W = 12, 64, 80
+    q = synth.video_levels(6, T, H, W)
+    top0, left0, rh, rw, vy, vx, lq = synth.video_rects(6, H, W)[-1]
+    for t in (0, 5, 11):
+        h = (top0 + vy * t) % H
+        w = (left0 + vx * t) % W
+        assert abs(int(q[t, h * W + w]) - int(np.clip(lq, -128, 127))) <= 18
