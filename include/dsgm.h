@@ -203,6 +203,44 @@ int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, 
                   double* grad_var_init, void* workspace, size_t workspace_bytes,
                   hipStream_t stream);
 
+/*
+ * Frame preprocessing (Sec. 2.1; serial and GPU versions in Sec. 3.1.1 and
+ * 3.3.1): a separable blur -- the n-tap kernel applied along rows, then along
+ * columns of the row-blurred frame, each sum taken from 0 in tap order -- then
+ * the median of every 3 x 3 neighbourhood of the blurred frame.  Indices
+ * outside the frame are clamped to the nearest valid row or column (the
+ * appendix clamps one past the last index; the last index is used).
+ */
+typedef struct {
+  int32_t n;           /* blur taps: 0 (no blur) or odd, 1..7 (n = 1: weight 1)   */
+  int32_t median;      /* 1: 3 x 3 median after the blur; 0: none                  */
+  double weights[7];   /* the n taps (host values), weights[(n-1)/2] the centre    */
+} dsgm_filter;
+
+/*
+ * The Sec. 2.1 Gaussian density sampled at the integer offsets d = i - (n-1)/2,
+ * e_i = exp(-(d*d) / (2*sigma*sigma)), normalised by their sum (taken in index
+ * order): w_i = e_i / sum.  n odd in 1..7, sigma > 0; writes n doubles to
+ * `weights` (host).  Returns DSGM_E_ARG on bad arguments.
+ */
+int dsgm_gauss_weights(int32_t n, double sigma, double* weights /* host, n */);
+
+/*
+ * dsgm_forward on the preprocessed frames, in one pass: the frames are read
+ * once per halo tile, filtered in LDS and fed to the update; the filtered
+ * frames are written only if `filtered` is not NULL (T x H x W, array type,
+ * strided like the frames).  masks, bg and codes as for dsgm_forward; no
+ * checkpoints (the adjoint does not run through the filters).  `filter` is a
+ * host struct; n > 7 returns DSGM_E_UNSUPPORTED.  With ACC_F64 the results are
+ * bit-identical to a scalar FP64 evaluation of the blur sums, the median and
+ * the update in the stated order.
+ */
+int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                          dsgm_acc acc, const dsgm_params* params /* host */,
+                          const dsgm_filter* filter /* host */, dsgm_state* state /* host struct */,
+                          uint8_t* masks, void* bg, void* filtered, uint8_t* codes,
+                          hipStream_t stream);
+
 /* one instance of a batch: its own sizes, strides, frames, state and outputs */
 typedef struct {
   dsgm_shape shape;

@@ -82,6 +82,11 @@ def lib():
         _lib.orc_jvp.argtypes = ([ctypes.c_int64, ctypes.c_int64] + [dp] * 11 +
                                  [ctypes.c_double, dp, dp, ctypes.c_int])
         _lib.orc_max_threads.restype = ctypes.c_int
+        _lib.orc_gauss_weights.argtypes = [ctypes.c_int32, ctypes.c_double, dp]
+        _lib.orc_gauss_weights.restype = ctypes.c_int
+        _lib.orc_preprocess.argtypes = ([ctypes.c_int64] * 3 + [dp, dp, ctypes.c_int32, dp,
+                                        ctypes.c_int32, ctypes.c_int])
+        _lib.orc_preprocess.restype = ctypes.c_int
         for f in (_lib.orc_forward, _lib.orc_backward, _lib.orc_jvp):
             f.restype = ctypes.c_int
     return _lib
@@ -198,3 +203,30 @@ def jvp(frames, state0: dict, params: Params, dframes, dstate0, dvar_init: float
     if rc != 0:
         raise ValueError(f"orc_jvp failed ({rc})")
     return {"dbg": dbg, "dstate_T": dsT}
+
+
+# ------------------------------------------------------------- preprocessing
+def gauss_weights(n: int, sigma: float) -> np.ndarray:
+    """Normalised Gaussian weights of length n (odd), Sec. 2.1 density sampled
+    at integer offsets from the centre (preprocess_oracle.c)."""
+    w = np.empty(n, np.float64)
+    if lib().orc_gauss_weights(int(n), float(sigma), _ptr(w)) != 0:
+        raise ValueError("orc_gauss_weights: bad arguments")
+    return w
+
+
+def preprocess(frames, weights=None, median: bool = True, nthreads: int = 0) -> np.ndarray:
+    """Separable blur with `weights` (rows, then columns; None = no blur), then
+    the 3 x 3 median (if `median`), borders clamped; frames (T, H, W) -> same."""
+    x = np.ascontiguousarray(frames, dtype=np.float64)
+    if x.ndim == 2:
+        x = x[None]
+    T, H, W = x.shape
+    out = np.empty_like(x)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    n = 0 if w is None else int(w.size)
+    rc = lib().orc_preprocess(T, H, W, _ptr(x), _ptr(out), n, _ptr(w), int(bool(median)),
+                              int(nthreads))
+    if rc != 0:
+        raise ValueError(f"orc_preprocess failed ({rc})")
+    return out

@@ -12,13 +12,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "dsgm_oracle.c")
+SRCS = [os.path.join(HERE, "dsgm_oracle.c"), os.path.join(HERE, "preprocess_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
-           "-std=c99", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-std=c99", "-Wall", "-Wextra", "-o", LIB + ".tmp"] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -343,6 +343,98 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   return ok();
 }
 
+int dsgm_gauss_weights(int32_t n, double sigma, double* weights) {
+  if (n < 1 || n > 7 || n % 2 == 0) return fail(DSGM_E_ARG, "blur taps n = %d (odd, 1..7)", n);
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(DSGM_E_ARG, "sigma must be > 0");
+  if (!weights) return fail(DSGM_E_ARG, "weights is NULL");
+  const int32_t r = (n - 1) / 2;
+  double sum = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    const double d = double(i - r);
+    weights[i] = std::exp(-(d * d) / (2.0 * sigma * sigma));
+    sum += weights[i];
+  }
+  for (int32_t i = 0; i < n; ++i) weights[i] = weights[i] / sum;
+  return ok();
+}
+
+int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                          dsgm_acc acc, const dsgm_params* params, const dsgm_filter* filter,
+                          dsgm_state* state, uint8_t* masks, void* bg, void* filtered,
+                          uint8_t* codes, hipStream_t stream) {
+  int rc;
+  if ((rc = check_types(in_dtype, acc))) return rc;
+  if ((rc = check_params(params))) return rc;
+  if (!filter) return fail(DSGM_E_ARG, "filter is NULL");
+  if (filter->n < 0 || (filter->n > 0 && filter->n % 2 == 0))
+    return fail(DSGM_E_ARG, "blur taps n = %d (0 or odd)", filter->n);
+  if (filter->n > 7) return fail(DSGM_E_UNSUPPORTED, "blur taps n = %d > 7", filter->n);
+  if (filter->n == 1 && filter->weights[0] != 1.0)
+    return fail(DSGM_E_UNSUPPORTED, "a one-tap blur must have weight 1");
+  if (filter->median != 0 && filter->median != 1)
+    return fail(DSGM_E_ARG, "median = %d (0 or 1)", filter->median);
+  for (int i = 0; i < filter->n; ++i)
+    if (!std::isfinite(filter->weights[i])) return fail(DSGM_E_ARG, "blur weight %d not finite", i);
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
+  if ((rc = check_shape(shape, ie > oe ? ie : oe))) return rc;
+  if (!state) return fail(DSGM_E_ARG, "state is NULL");
+  if (shape.H * shape.W == 0 || shape.T == 0) return ok();
+  if (!frames) return fail(DSGM_E_ARG, "frames is NULL");
+  if (!masks) return fail(DSGM_E_ARG, "masks is NULL");
+  if (!state->mean_a || !state->var_a || !state->mean_c || !state->var_c || !state->age_a ||
+      !state->age_c)
+    return fail(DSGM_E_ARG, "a state plane is NULL");
+  const void* ptrs[10] = {frames, masks, bg, codes, filtered, state->mean_a, state->var_a,
+                          state->mean_c, state->var_c, nullptr};
+  const size_t elem[10] = {ie, 1, oe, 1, oe, ae, ae, ae, ae, 1};
+  for (int i = 0; i < 9; ++i)
+    if (ptrs[i] && !aligned(ptrs[i], elem[i]))
+      return fail(DSGM_E_ALIGN, "pointer argument %d is not aligned to %zu bytes", i, elem[i]);
+  // the kernel writes four adjacent pixels with one vector store when the row
+  // and frame strides and W are multiples of four; the bases must allow it
+  const void* vec_ptrs[4] = {masks, bg, codes, filtered};
+  const size_t vec_elem[4] = {1, oe, 1, oe};
+  for (int i = 0; i < 4; ++i)
+    if (vec_ptrs[i] && !aligned(vec_ptrs[i], 4 * vec_elem[i]))
+      return fail(DSGM_E_ALIGN, "output %d is not aligned to %zu bytes", i, 4 * vec_elem[i]);
+
+  dsgm::PreArgs a;
+  memset(&a, 0, sizeof(a));
+  a.frames = frames;
+  a.masks = masks;
+  a.bg = bg;
+  a.filtered = filtered;
+  a.codes = codes;
+  a.mean_a = state->mean_a;
+  a.var_a = state->var_a;
+  a.mean_c = state->mean_c;
+  a.var_c = state->var_c;
+  a.age_a = state->age_a;
+  a.age_c = state->age_c;
+  a.T = shape.T;
+  a.H = shape.H;
+  a.W = shape.W;
+  a.row_stride = shape.row_stride;
+  a.frame_stride = shape.frame_stride;
+  a.tiles_x = (shape.W + 63) / 64;
+  a.tiles_y = (shape.H + 15) / 16;
+  if (a.tiles_x * a.tiles_y >= (int64_t(1) << 31))
+    return fail(DSGM_E_SHAPE, "too many tiles");
+  a.theta_s = params->theta_s;
+  a.theta_d = params->theta_d;
+  a.var_init = params->var_init;
+  a.var_floor = params->var_floor;
+  a.mask_floor = params->mask_floor;
+  a.age_max = params->age_max;
+  a.weight_rule = params->weight_rule;
+  a.mask_rule = params->mask_rule;
+  for (int i = 0; i < filter->n; ++i) a.w[i] = filter->weights[i];
+  const int rg = filter->n > 0 ? (filter->n - 1) / 2 : 0;  // n = 1 (weight 1) is no blur
+  hipError_t e = dsgm::launch_pre(a, in_dtype, acc, rg, filter->median != 0, stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_forward_filtered launch");
+  return ok();
+}
+
 size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc) {
   if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32) return 0;
   if (shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;

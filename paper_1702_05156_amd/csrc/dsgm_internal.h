@@ -91,6 +91,30 @@ struct BatchArgs {
   int32_t age_max, weight_rule, mask_rule;
 };
 
+// Arguments of the forward with fused preprocessing (dsgm_pre.hip).
+struct PreArgs {
+  const void* frames;
+  uint8_t* masks;
+  void* bg;        // NULL: none
+  void* filtered;  // NULL: none; the preprocessed frames, array type
+  uint8_t* codes;  // NULL: none
+  void* mean_a;
+  void* var_a;
+  void* mean_c;
+  void* var_c;
+  uint8_t* age_a;
+  uint8_t* age_c;
+  int64_t T, H, W, row_stride, frame_stride;
+  int64_t tiles_x, tiles_y;
+  double theta_s, theta_d, var_init, var_floor, mask_floor;
+  int32_t age_max, weight_rule, mask_rule;
+  double w[7];  // blur weights, 2*rg+1 of them
+};
+
+// rg: blur radius 0..3 (0: no blur); median: 3 x 3 median after the blur
+hipError_t launch_pre(const PreArgs& a, int in_dtype, int acc, int rg, bool median,
+                      hipStream_t stream);
+
 // Variant flags of the forward kernels (see dsgm_fwd_impl.h).
 enum : int { FWD_BG = 1, FWD_CODES = 2, FWD_CKPT = 4, FWD_PRINTED = 8 };
 

@@ -57,6 +57,12 @@ class Shape(ctypes.Structure):
                 ("row_stride", ctypes.c_int64), ("frame_stride", ctypes.c_int64)]
 
 
+class Filter(ctypes.Structure):
+    """dsgm_filter (host struct): n-tap separable blur, then an optional 3 x 3 median."""
+    _fields_ = [("n", ctypes.c_int32), ("median", ctypes.c_int32),
+                ("weights", ctypes.c_double * 7)]
+
+
 class _State(ctypes.Structure):
     _fields_ = [("mean_a", ctypes.c_void_p), ("var_a", ctypes.c_void_p),
                 ("mean_c", ctypes.c_void_p), ("var_c", ctypes.c_void_p),
@@ -94,6 +100,10 @@ def _load():
     sz = ctypes.c_size_t
     lib.dsgm_forward.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params),
                                  ctypes.POINTER(_State), vp, vp, vp, sz, i32, vp, vp]
+    lib.dsgm_gauss_weights.argtypes = [i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    lib.dsgm_forward_filtered.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params),
+                                          ctypes.POINTER(Filter), ctypes.POINTER(_State), vp, vp,
+                                          vp, vp, vp]
     lib.dsgm_ckpt_bytes.argtypes = [Shape, i32, i32]
     lib.dsgm_ckpt_bytes.restype = ctypes.c_size_t
     lib.dsgm_workspace_bytes.argtypes = [Shape, i32]
@@ -112,7 +122,7 @@ def _load():
     lib.dsgm_set_launch.argtypes = [i32, i32]
     for f in ("dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
               "dsgm_backward", "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_version",
-              "dsgm_set_launch"):
+              "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered"):
         getattr(lib, f).restype = ctypes.c_int
     del i64
     return lib
@@ -124,7 +134,7 @@ lib = _load()
 EXPORTS = ["dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
            "dsgm_ckpt_bytes", "dsgm_workspace_bytes", "dsgm_backward", "dsgm_batch_plan_bytes",
            "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_status_string", "dsgm_last_error",
-           "dsgm_version", "dsgm_set_launch"]
+           "dsgm_version", "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered"]
 
 
 def _check(fn: str, rc: int):
@@ -261,6 +271,45 @@ def dsgm_forward(frames: torch.Tensor, state: State, params: Params, masks: torc
                             _stream()))
 
 
+def dsgm_gauss_weights(n: int = 5, sigma: float = 1.0) -> list:
+    """The n normalised Gaussian taps (Sec. 2.1 density at integer offsets)."""
+    w = (ctypes.c_double * 7)()
+    _check("dsgm_gauss_weights", lib.dsgm_gauss_weights(int(n), float(sigma), w))
+    return [w[i] for i in range(n)]
+
+
+def gauss_filter(n: int = 5, sigma: float = 1.0, median: bool = True) -> Filter:
+    """The paper's preprocessing: an n-tap Gaussian blur, then a 3 x 3 median."""
+    f = Filter()
+    f.n = int(n)
+    f.median = int(bool(median))
+    for i, v in enumerate(dsgm_gauss_weights(n, sigma) if n else []):
+        f.weights[i] = v
+    return f
+
+
+def dsgm_forward_filtered(frames: torch.Tensor, state: State, params: Params, filt: Filter,
+                          masks: torch.Tensor, bg: torch.Tensor | None = None,
+                          filtered: torch.Tensor | None = None, codes: torch.Tensor | None = None,
+                          acc=None) -> None:
+    """dsgm_forward on the preprocessed frames (blur, then median), fused in one pass;
+    ``filtered`` (optional) receives the preprocessed frames."""
+    if frames.dtype not in _IN_DTYPES:
+        raise TypeError(f"frames dtype {frames.dtype} not supported")
+    sh = _frames_shape(frames)
+    acc = _resolve_acc(state, acc)
+    _same_layout("masks", masks, frames, torch.uint8)
+    _same_layout("bg", bg, frames, ACC_TORCH[acc])
+    _same_layout("filtered", filtered, frames, ACC_TORCH[acc])
+    _same_layout("codes", codes, frames, torch.uint8)
+    cs = _cstate(state, sh.H, sh.W)
+    _check("dsgm_forward_filtered",
+           lib.dsgm_forward_filtered(_ptr(frames), _IN_DTYPES[frames.dtype], sh, acc,
+                                     ctypes.byref(params), ctypes.byref(filt), ctypes.byref(cs),
+                                     _ptr(masks), _ptr(bg), _ptr(filtered), _ptr(codes),
+                                     _stream()))
+
+
 def dsgm_workspace_bytes(T: int, H: int, W: int, acc: int) -> int:
     return int(lib.dsgm_workspace_bytes(Shape(T, H, W, W, H * W), acc))
 
@@ -324,6 +373,24 @@ def forward(frames: torch.Tensor, state: State, params: Params, *, bg: bool = Fa
                                   dtype=torch.uint8, device=frames.device)
     dsgm_forward(frames, state, params, out["masks"], out.get("bg"), out.get("ckpt"), ckpt_every,
                  out.get("codes"), acc=acc)
+    return out
+
+
+def forward_filtered(frames: torch.Tensor, state: State, params: Params, filt: Filter, *,
+                     bg: bool = False, filtered: bool = False, codes: bool = False,
+                     acc=None) -> dict:
+    """Allocate the outputs and call dsgm_forward_filtered."""
+    acc = _resolve_acc(state, acc)
+    like = lambda dt: torch.empty_strided(frames.shape, frames.stride(), dtype=dt, device=frames.device)
+    out = {"masks": like(torch.uint8)}
+    if bg:
+        out["bg"] = like(ACC_TORCH[acc])
+    if filtered:
+        out["filtered"] = like(ACC_TORCH[acc])
+    if codes:
+        out["codes"] = like(torch.uint8)
+    dsgm_forward_filtered(frames, state, params, filt, out["masks"], out.get("bg"),
+                          out.get("filtered"), out.get("codes"), acc=acc)
     return out
 
 

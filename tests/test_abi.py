@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -175,3 +176,42 @@ def test_batched_validation():
     assert lib.dsgm_forward_batched(ctypes.byref(plan), ctypes.byref(p), None) == -1
     plan.vector, plan.n_items = 4, 0
     assert lib.dsgm_forward_batched(ctypes.byref(plan), ctypes.byref(p), None) == 0  # nothing to do
+
+
+E_ARG, E_UNSUPPORTED = -1, -7
+
+
+def test_gauss_weights_match_the_oracle():
+    """The library's Gaussian taps (host code) equal the oracle's bit for bit
+    (both evaluate the Sec. 2.1 density in the same stated order)."""
+    import oracle
+    for n, sigma in [(1, 1.0), (3, 0.7), (5, 1.0), (7, 1.5)]:
+        got = np.array(dsgm.dsgm_gauss_weights(n, sigma))
+        assert np.array_equal(got, oracle.gauss_weights(n, sigma)), (n, sigma)
+
+
+def test_filtered_forward_validation():
+    """Argument checks of dsgm_forward_filtered run before any HIP call."""
+    p = dsgm.dsgm_params_default(2.0)
+    sh = dsgm.Shape(4, 8, 8, 8, 64)
+    st = dsgm._State(16, 16, 16, 16, 16, 16)
+    for n, med, want in [(4, 1, E_ARG), (9, 1, E_UNSUPPORTED), (5, 2, E_ARG),
+                         (-1, 0, E_ARG)]:
+        f = dsgm.Filter()
+        f.n, f.median = n, med
+        for i in range(7):
+            f.weights[i] = 0.2
+        rc = dsgm.lib.dsgm_forward_filtered(16, 0, sh, 0, ctypes.byref(p), ctypes.byref(f),
+                                            ctypes.byref(st), 16, None, None, None, None)
+        assert rc == want, (n, med, rc)
+    f = dsgm.gauss_filter(5, 1.0)
+    rc = dsgm.lib.dsgm_forward_filtered(16, 0, sh, 0, ctypes.byref(p), None, ctypes.byref(st),
+                                        16, None, None, None, None)
+    assert rc == E_ARG
+    f.n, f.weights[0] = 1, 0.5
+    rc = dsgm.lib.dsgm_forward_filtered(16, 0, sh, 0, ctypes.byref(p), ctypes.byref(f),
+                                        ctypes.byref(st), 16, None, None, None, None)
+    assert rc == E_UNSUPPORTED
+    for n, s in [(4, 1.0), (9, 1.0), (5, 0.0)]:
+        with pytest.raises(dsgm.DSGMError):
+            dsgm.dsgm_gauss_weights(n, s)

@@ -1,0 +1,114 @@
+"""GPU parity of the forward with fused preprocessing (dsgm_forward_filtered):
+the separable blur and the 3 x 3 median (Sec. 2.1, 3.3.1) feeding the update,
+against the preprocessing oracle followed by the update oracle.  FP64 is
+bit-exact (same sums in the same order, exact median selection); FP32 state
+is held to the certified tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from synth import device as sdev
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+
+
+
+def _case(seed, T, H, W, n, median, in_dtype=torch.float64, sigma=1.0, frames=None):
+    p = dsgm.dsgm_params_default(2.0)
+    filt = dsgm.gauss_filter(n, sigma, median) if n else dsgm.gauss_filter(0, 1.0, median)
+    fr, st = G.device_case(seed, T, H, W, in_dtype, torch.float64)
+    if frames is not None:
+        fr = frames(fr)
+    out = dsgm.forward_filtered(fr, st, p, filt, bg=True, filtered=True, codes=True)
+    torch.cuda.synchronize()
+    x, st0 = G.host_case(seed, T, H, W, in_dtype, torch.float64)
+    w = oracle.gauss_weights(n, sigma) if n else None
+    xf = oracle.preprocess(x.reshape(T, H, W), w, median=bool(median)).reshape(T, H * W)
+    return p, out, st, xf, st0
+
+
+@pytest.mark.parametrize("n,median", [(5, 1), (3, 1), (7, 1), (5, 0), (0, 1), (0, 0), (1, 1)])
+def test_filtered_frames_and_update_f64_bit_exact(n, median):
+    T, H, W = 23, 37, 150   # several tiles, ragged in both directions
+    p, out, st, xf, st0 = _case(41, T, H, W, n, median)
+    G.assert_bit_exact("filtered", G.flat(out["filtered"]), xf)
+    ref = oracle.forward(xf, st0, G.oracle_params(p))
+    G.assert_bit_exact("codes", G.flat(out["codes"]), ref["codes"])
+    G.assert_bit_exact("masks", G.flat(out["masks"]), ref["masks"])
+    G.assert_bit_exact("bg", G.flat(out["bg"]), ref["bg"])
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k], ref[k])
+
+
+@pytest.mark.parametrize("T,H,W", [(3, 1, 1), (4, 1, 70), (4, 70, 1), (5, 16, 64), (2, 17, 65),
+                                   (1, 2, 3)])
+def test_filtered_edge_shapes(T, H, W):
+    p, out, st, xf, st0 = _case(42, T, H, W, 5, 1)
+    G.assert_bit_exact("filtered", G.flat(out["filtered"]), xf)
+    ref = oracle.forward(xf, st0, G.oracle_params(p))
+    G.assert_bit_exact("masks", G.flat(out["masks"]), ref["masks"])
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k], ref[k])
+
+
+def test_filtered_strided_frames():
+    """Frames that are a view with row and frame padding (scalar stores)."""
+    T, H, W = 9, 20, 70
+
+    def pad(fr):
+        big = torch.zeros((T, H + 3, W + 5), dtype=fr.dtype, device=fr.device)
+        big[:, :H, :W] = fr
+        return big[:, :H, :W]
+    p, out, st, xf, st0 = _case(43, T, H, W, 5, 1, frames=pad)
+    G.assert_bit_exact("filtered", G.flat(out["filtered"]), xf)
+    ref = oracle.forward(xf, st0, G.oracle_params(p))
+    G.assert_bit_exact("masks", G.flat(out["masks"]), ref["masks"])
+
+
+def test_filtered_video_f64_bit_exact():
+    """The structured video from a state initialised on the first filtered frame."""
+    T, H, W = 120, 48, 96
+    p = dsgm.dsgm_params_default(2.0)
+    filt = dsgm.gauss_filter(5, 1.0, True)
+    fr = sdev.video(44, T, H, W, torch.float64)
+    x = synth.video(44, T, H, W)
+    xf = oracle.preprocess(x.reshape(T, H, W), oracle.gauss_weights(5, 1.0)).reshape(T, H * W)
+    st = dsgm.State.empty(H, W)
+    ff0 = torch.as_tensor(xf[0].reshape(H, W), device="cuda")
+    dsgm.dsgm_state_init_from_frame(ff0, st, p)
+    out = dsgm.forward_filtered(fr, st, p, filt, filtered=True, codes=True)
+    torch.cuda.synchronize()
+    G.assert_bit_exact("filtered", G.flat(out["filtered"]), xf)
+    n = H * W
+    st0 = {"mean_a": xf[0].copy(), "mean_c": xf[0].copy(), "var_a": np.full(n, p.var_init),
+           "var_c": np.full(n, p.var_init), "age_a": np.ones(n, np.int32),
+           "age_c": np.ones(n, np.int32)}
+    ref = oracle.forward(xf, st0, G.oracle_params(p))
+    G.assert_bit_exact("codes", G.flat(out["codes"]), ref["codes"])
+
+
+@pytest.mark.parametrize("in_dtype", [torch.bfloat16, torch.float32])
+def test_filtered_fp32_within_tolerance(in_dtype):
+    """FP32 state and arithmetic (the blur with fused multiply-adds): the
+    filtered frames agree with the FP64 oracle to 1e-6; decisions that differ
+    are certified near ties of the oracle run on the oracle's filtered frames."""
+    from tests.test_gpu_forward import _certify_fp32
+    T, H, W, seed = 60, 64, 128, 45
+    p = dsgm.dsgm_params_default(2.0)
+    filt = dsgm.gauss_filter(5, 1.0, True)
+    fr, st = G.device_case(seed, T, H, W, in_dtype, torch.float32)
+    out = dsgm.forward_filtered(fr, st, p, filt, bg=True, filtered=True, codes=True)
+    torch.cuda.synchronize()
+    x, st0 = G.host_case(seed, T, H, W, in_dtype, torch.float32)
+    xf = oracle.preprocess(x.reshape(T, H, W), oracle.gauss_weights(5, 1.0)).reshape(T, H * W)
+    assert np.max(np.abs(G.flat(out["filtered"]) - xf)) <= 1e-6
+    ref = oracle.forward(xf, st0, G.oracle_params(p), margins=True)
+    div = _certify_fp32(G.flat(out["codes"]), ref, tol_margin=1e-5)
+    assert div.mean() <= 1e-3, div.mean()
