@@ -2,7 +2,7 @@
 """Throughput of the DSGM hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--legs main,mixed,video,attainable,adjoint,batched,largest]
+                    [--legs main,mixed,video,filtered,attainable,adjoint,batched,largest]
                     [--no-cpu-baseline]
 
 Main workload (the `value`): the plain method in FP64, one instance of
@@ -20,6 +20,8 @@ Secondary legs, reported under "legs" (same timing method):
   video    the same size on a structured video (static background, exposure step,
            moving rectangles, 8-bit levels) from a state initialised from frame 0:
            FP64 and BF16/FP32 throughput on a realistic decision mix
+  filtered the main workload with the paper's preprocessing (Gaussian blur, 3x3
+           median) fused into the forward, FP64 and BF16/FP32
   attainable  the same bytes as the forward and backward kernels moved by kernels
            with no model arithmetic: the attainable HBM rate of each access pattern
   adjoint  FP32 frames and state, bg on, checkpoints every 32 frames, upstream
@@ -53,11 +55,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def source_hash() -> str:
+# the sources a kernel is compiled from: its translation unit and the headers
+# that unit includes (a change anywhere else does not change the kernel)
+KERNEL_SOURCES = {
+    "fwd_kernel_f64_f64_p2": ["dsgm_fwd_f64_f64.hip", "dsgm_fwd_impl.h", "dsgm_internal.h",
+                              "dsgm_device.h"],
+}
+
+
+def source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1702_05156_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode() + fh.read())
+    for name in sorted(KERNEL_SOURCES[kernel]):
+        with open(os.path.join(ROOT, "paper_1702_05156_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -69,7 +79,7 @@ def load_traffic(kernel: str):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash(kernel):
         return None
     return d.get("traffic_bytes_per_launch")
 
@@ -100,6 +110,11 @@ def cpu_baseline(T, H, W, seed, target_s=10.0, chunk_rows=32):
     return {"value": n / dt, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": f"rows 0-{done_rows - 1} of {H} x {W} columns x {T} frames = {n} elements "
                       f"(FP64 scalar C, OpenMP over pixel chunks), {dt:.2f} s of oracle time"}
+
+
+def progress(msg: str) -> None:
+    """One progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def timed(fn, steps, warmup, stream):
@@ -198,6 +213,31 @@ def leg_video(args, dsgm, sdev, torch):
         dsgm.dsgm_state_init_from_frame(fr[0], st, p)
         masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
         ms, kk = timed(lambda: dsgm.dsgm_forward(fr, st, p, masks), steps, 1, stream)
+        out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                     "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)))}
+        del fr, st, masks
+        torch.cuda.empty_cache()
+    return out
+
+
+def leg_filtered(args, dsgm, sdev, torch):
+    """The forward with the paper's preprocessing fused in (5-tap Gaussian,
+    sigma 1, then the 3x3 median): the main workload's frames and state (FP64),
+    and BF16 frames with FP32 state."""
+    T, H, W, seed = 500, 1920, 2560, 1
+    p = dsgm.dsgm_params_default(2.0)
+    filt = dsgm.gauss_filter(5, 1.0, True)
+    stream = torch.cuda.current_stream()
+    elems, px = T * H * W, H * W
+    steps = max(3, args.steps // 2)
+    out = {"workload": "1920x2560x500 seed 1, masks only, 5-tap Gaussian (sigma 1) + 3x3 median "
+                       "fused into the forward"}
+    for name, in_dt, acc_dt, in_b, st_b in (("fp64", torch.float64, torch.float64, 8, 68),
+                                             ("bf16_fp32", torch.bfloat16, torch.float32, 2, 36)):
+        fr = sdev.frames(seed, T, H, W, in_dt)
+        st = dsgm.State(*sdev.state(seed, H, W, acc_dt))
+        masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+        ms, kk = timed(lambda: dsgm.dsgm_forward_filtered(fr, st, p, filt, masks), steps, 1, stream)
         out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
                      "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)))}
         del fr, st, masks
@@ -360,8 +400,9 @@ def _batch_items(shapes, idx, dsgm, sdev, torch, frames_dtype, state_dtype, st0)
         if frames_dtype != torch.bfloat16:
             fr = fr.to(frames_dtype)
         s = st0[i]
-        st = dsgm.State(s.mean_a.to(state_dtype), s.var_a.to(state_dtype), s.mean_c.to(state_dtype),
-                        s.var_c.to(state_dtype), s.age_a.clone(), s.age_c.clone())
+        cp = lambda t: t.to(dtype=state_dtype, copy=True)  # never the initial state itself
+        st = dsgm.State(cp(s.mean_a), cp(s.var_a), cp(s.mean_c), cp(s.var_c), s.age_a.clone(),
+                        s.age_c.clone())
         items.append((fr, st, torch.empty((T, H, W), dtype=torch.uint8, device="cuda"), None))
     return items
 
@@ -458,7 +499,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="main,mixed,video,attainable,adjoint,batched,largest")
+    ap.add_argument("--legs", default="main,mixed,video,filtered,attainable,adjoint,batched,largest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
@@ -513,20 +554,18 @@ def main():
     torch.cuda.empty_cache()
 
     out_legs = {}
-    if "mixed" in legs:
-        out_legs["mixed"] = leg_mixed(args, dsgm, sdev, torch)
-    if "video" in legs:
-        out_legs["video"] = leg_video(args, dsgm, sdev, torch)
-    if "attainable" in legs:
-        out_legs["attainable"] = leg_attainable(args, dsgm, sdev, torch)
-    if "adjoint" in legs:
-        out_legs["adjoint"] = leg_adjoint(args, dsgm, sdev, torch)
-    if "batched" in legs:
-        out_legs["batched"] = leg_batched(args, dsgm, sdev, torch)
-    if "largest" in legs:
-        out_legs["largest"] = leg_largest(args, dsgm, sdev, torch)
+    progress(f"main leg done: {value / 1e9:.1f} G elements/s")
+    for name, fn in (("mixed", leg_mixed), ("video", leg_video), ("filtered", leg_filtered),
+                     ("attainable", leg_attainable), ("adjoint", leg_adjoint),
+                     ("batched", leg_batched), ("largest", leg_largest)):
+        if name in legs:
+            t0 = time.perf_counter()
+            out_legs[name] = fn(args, dsgm, sdev, torch)
+            progress(f"{name} leg done in {time.perf_counter() - t0:.1f} s")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(T, H, W, seed)
+    if cpu is not None:
+        progress("cpu baseline done")
 
     out = {
         "metric": "hot-path elements/s and % roofline (fwd+adjoint), mixed vs FP64 at tol",
