@@ -91,10 +91,13 @@ template <typename In, typename Acc, typename Io, int RG, bool MED>
 __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
   using G = Geo<RG, MED>;
   constexpr int R = G::R, RM = G::RM;
-  // raw tile and column-blurred tile share storage (the raw tile is dead once
-  // the row pass is done); the row-blurred tile has its own
-  __shared__ Acc buf_raw[G::RAW_N > G::GB_N ? G::RAW_N : G::GB_N];
+  // raw, row-blurred and blurred tiles each have their own storage, so a frame
+  // needs three barriers: the next frame's raw tile can be staged while slow
+  // lanes still read this frame's blurred tile (without a blur the raw tile is
+  // the blurred tile and a fourth barrier guards it)
+  __shared__ Acc buf_raw[G::RAW_N];
   __shared__ Acc buf_hb[RG > 0 ? G::HB_N : 1];
+  __shared__ Acc buf_gb[RG > 0 ? G::GB_N : 1];
   __shared__ TableEntry<Acc> tbl[TABLE_SIZE];
   fill_table<Acc>(tbl, a.weight_rule, a.age_max, a.var_init);  // ends with a barrier
   const StepConsts<Acc> k =
@@ -176,27 +179,42 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
 
     const Acc* gbp;  // the blurred tile, GB_H x GB_W
     if constexpr (RG > 0) {
-      // 2. row pass: hb[r][v] = sum_j w_j raw[r][v + j], v in [0, HB_W)
-      for (int i = tid; i < G::HB_N; i += NT) {
-        const int r = i / G::HB_W, v = i - r * G::HB_W;
+      // 2. row pass: hb[r][v] = sum_j w_j raw[r][v + j], v in [0, HB_W).  A
+      // lane makes two horizontally adjacent outputs per step from one window
+      // of 2*RG + 2 values (HB_W is even, so a pair never straddles rows)
+      static_assert(G::HB_W % 2 == 0 && G::GB_W % 2 == 0, "output pairs stay in one row");
+      for (int pi = tid; pi < G::HB_N / 2; pi += NT) {
+        const int r = pi / (G::HB_W / 2), v = 2 * (pi - r * (G::HB_W / 2));
         const Acc* src = buf_raw + r * G::RAW_W + v;
-        Acc acc = Acc(0);
+        Acc win[2 * RG + 2];
 #pragma unroll
-        for (int j = 0; j < 2 * RG + 1; ++j) acc = tap(acc, wt[j], src[j]);
-        buf_hb[i] = acc;
+        for (int j = 0; j < 2 * RG + 2; ++j) win[j] = src[j];
+        Acc a0 = Acc(0), a1 = Acc(0);
+#pragma unroll
+        for (int j = 0; j < 2 * RG + 1; ++j) {
+          a0 = tap(a0, wt[j], win[j]);
+          a1 = tap(a1, wt[j], win[j + 1]);
+        }
+        buf_hb[2 * pi] = a0;
+        buf_hb[2 * pi + 1] = a1;
       }
       __syncthreads();
-      // 3. column pass: gb[r][v] = sum_i w_i hb[r + i][v], r in [0, GB_H)
-      for (int i = tid; i < G::GB_N; i += NT) {
-        const int r = i / G::GB_W, v = i - r * G::GB_W;
-        const Acc* src = buf_hb + r * G::HB_W + v;
-        Acc acc = Acc(0);
+      // 3. column pass: gb[r][v] = sum_i w_i hb[r + i][v], r in [0, GB_H); the
+      // two tiles have the same width, so gb's row-major index is hb's
+      static_assert(G::HB_W == G::GB_W, "row-blurred and blurred tiles share a width");
+      for (int pi = tid; pi < G::GB_N / 2; pi += NT) {
+        const Acc* src = buf_hb + 2 * pi;
+        Acc a0 = Acc(0), a1 = Acc(0);
 #pragma unroll
-        for (int j = 0; j < 2 * RG + 1; ++j) acc = tap(acc, wt[j], src[j * G::HB_W]);
-        buf_raw[i] = acc;
+        for (int j = 0; j < 2 * RG + 1; ++j) {
+          a0 = tap(a0, wt[j], src[j * G::HB_W]);
+          a1 = tap(a1, wt[j], src[j * G::HB_W + 1]);
+        }
+        buf_gb[2 * pi] = a0;
+        buf_gb[2 * pi + 1] = a1;
       }
       __syncthreads();
-      gbp = buf_raw;
+      gbp = buf_gb;
     } else {
       gbp = buf_raw;  // no blur: the raw tile (R = RM) is the blurred tile
     }
@@ -266,7 +284,7 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
         if (a.codes) a.codes[o + q] = cd.v[q];
       }
     }
-    __syncthreads();  // the next frame overwrites the tiles
+    if constexpr (RG == 0) __syncthreads();  // the next frame overwrites the raw tile
   }
 
 #pragma unroll
