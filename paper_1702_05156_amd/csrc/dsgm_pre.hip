@@ -61,10 +61,12 @@ __device__ __forceinline__ int64_t clampi(int64_t v, int64_t hi) {
   return v < 0 ? 0 : (v > hi ? hi : v);
 }
 
-template <typename Acc>
-__device__ __forceinline__ Acc mn(Acc a, Acc b) { return b < a ? b : a; }
-template <typename Acc>
-__device__ __forceinline__ Acc mx(Acc a, Acc b) { return a < b ? b : a; }
+// min and max of finite values (v_min/v_max; a zero's sign may differ from a
+// sort's when +0 and -0 tie, which leaves every value unchanged)
+__device__ __forceinline__ double mn(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ double mx(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float mn(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ float mx(float a, float b) { return __builtin_fmaxf(a, b); }
 
 // median of three
 template <typename Acc>
@@ -116,13 +118,13 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
   const int64_t H1 = a.H - 1, W1 = a.W - 1;
 
   // this lane's raw-tile elements: LDS slot and frame offset (both fixed per frame)
-  int32_t roff[G::LOADS];
+  uint32_t roff[G::LOADS];
 #pragma unroll
   for (int l = 0; l < G::LOADS; ++l) {
     const int i = tid + l * NT;
     const int r = i / G::RAW_W, c = i - r * G::RAW_W;
     const int64_t yy = clampi(y0 - R + r, H1), xx = clampi(x0 - R + c, W1);
-    roff[l] = i < G::RAW_N ? int32_t(yy * a.row_stride + xx) : 0;  // < 2^31 (host check)
+    roff[l] = i < G::RAW_N ? uint32_t(yy * a.row_stride + xx) : 0u;  // < 2^31 (host check)
   }
   // the median's rows and columns in the blurred tile, clamped to the frame
   int gr[3], gc[PX + 2];
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
     const In* f = frames + t * a.frame_stride;
 #pragma unroll
     for (int l = 0; l < G::LOADS; ++l)
-      if (tid + l * NT < G::RAW_N) nxt[l] = f[roff[l]];
+      if (l + 1 < G::LOADS || tid + l * NT < G::RAW_N) nxt[l] = f[roff[l]];  // tid < NT
   };
   if (a.T > 0) load_frame(0);
 
@@ -173,7 +175,8 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
     // 1. stage the raw tile, then start loading the next frame's
 #pragma unroll
     for (int l = 0; l < G::LOADS; ++l)
-      if (tid + l * NT < G::RAW_N) buf_raw[tid + l * NT] = to_acc<In, Acc>(nxt[l]);
+      if (l + 1 < G::LOADS || tid + l * NT < G::RAW_N)
+        buf_raw[tid + l * NT] = to_acc<In, Acc>(nxt[l]);
     __syncthreads();
     if (t + 1 < a.T) load_frame(t + 1);
 
