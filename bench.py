@@ -2,7 +2,7 @@
 """Throughput of the DSGM hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--legs main,mixed,video,filtered,attainable,adjoint,batched,largest]
+                    [--legs main,mixed,video,filtered,warped,attainable,adjoint,batched,largest]
                     [--no-cpu-baseline]
 
 Main workload (the `value`): the plain method in FP64, one instance of
@@ -22,6 +22,8 @@ Secondary legs, reported under "legs" (same timing method):
            FP64 and BF16/FP32 throughput on a realistic decision mix
   filtered the main workload with the paper's preprocessing (Gaussian blur, 3x3
            median) fused into the forward, FP64 and BF16/FP32
+  warped   motion-compensated update: 100 frames, one launch per frame, each with
+           its own camera homography (the model is gathered through it), FP64
   attainable  the same bytes as the forward and backward kernels moved by kernels
            with no model arithmetic: the attainable HBM rate of each access pattern
   adjoint  FP32 frames and state, bg on, checkpoints every 32 frames, upstream
@@ -242,6 +244,44 @@ def leg_filtered(args, dsgm, sdev, torch):
                      "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)))}
         del fr, st, masks
         torch.cuda.empty_cache()
+    return out
+
+
+def leg_warped(args, dsgm, sdev, torch):
+    """Motion-compensated update: 100 frames of 1920x2560 (FP64 frames and state,
+    seed 1), each with its own small camera homography (shift of up to 1.5
+    pixels and a rotation of up to 0.01 rad, seed 5), one launch per frame
+    ping-ponging two state buffers; element = one pixel-frame update."""
+    import numpy as np
+    T, H, W, seed = 100, 1920, 2560, 1
+    p = dsgm.dsgm_params_default(2.0)
+    stream = torch.cuda.current_stream()
+    fr = sdev.frames(seed, T, H, W, torch.float64)
+    a = dsgm.State(*sdev.state(seed, H, W, torch.float64))
+    b = dsgm.State.empty(H, W)
+    masks = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(5)
+    maps = []
+    for _ in range(T):
+        m = np.eye(3)
+        m[0, 2], m[1, 2] = rng.uniform(-1.5, 1.5, size=2)
+        m[0, 1], m[1, 0] = rng.uniform(-0.01, 0.01, size=2)
+        maps.append(m)
+    bufs = [a, b]
+
+    def run():
+        for t in range(T):
+            dsgm.dsgm_forward_warped(fr[t], bufs[t % 2], bufs[1 - t % 2], p, maps[t], masks)
+
+    steps = max(2, args.steps // 4)
+    ms, kk = timed(run, steps, 1, stream)
+    elems = T * H * W
+    alg = elems * (8 + 1 + 34 + 34)
+    out = {"workload": "1920x2560 x 100 frames, fp64, one launch per frame, per-frame homography",
+           "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+           "roofline": roof(alg, float(sum(kk) / len(kk)))}
+    del fr, a, b, masks, bufs
+    torch.cuda.empty_cache()
     return out
 
 
@@ -499,7 +539,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="main,mixed,video,filtered,attainable,adjoint,batched,largest")
+    ap.add_argument("--legs",
+                    default="main,mixed,video,filtered,warped,attainable,adjoint,batched,largest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
@@ -556,6 +597,7 @@ def main():
     out_legs = {}
     progress(f"main leg done: {value / 1e9:.1f} G elements/s")
     for name, fn in (("mixed", leg_mixed), ("video", leg_video), ("filtered", leg_filtered),
+                     ("warped", leg_warped),
                      ("attainable", leg_attainable), ("adjoint", leg_adjoint),
                      ("batched", leg_batched), ("largest", leg_largest)):
         if name in legs:

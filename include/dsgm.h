@@ -241,6 +241,34 @@ int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape
                           uint8_t* masks, void* bg, void* filtered, uint8_t* codes,
                           hipStream_t stream);
 
+/*
+ * One frame of the update on the motion-compensated model (Sec. 2.2 uses the
+ * previous values "after motion compensation"; Sec. 2.4 maps the per-pixel
+ * model through the camera's homography).  The homography is an input (its
+ * estimation, KLT tracking and RANSAC in the paper, is the caller's):
+ *   inv_map   host, 9 doubles, row-major: takes a pixel (column c, row y, 1)
+ *             of the current frame to the previous frame,
+ *             den = (m6*c + m7*y) + m8, qx = ((m0*c + m1*y) + m2) / den,
+ *             qy = ((m3*c + m4*y) + m5) / den
+ * A pixel with den > 0 and (qx, qy) inside [0, W-1] x [0, H-1] takes from
+ * `src` the bilinear blend of the four surrounding means and variances
+ * (weights (1-fx)(1-fy), fx(1-fy), (1-fx)fy, fx*fy, fx = qx - floor(qx), in
+ * that order; an index past the last row or column is clamped, its weight is
+ * 0) and the nearest pixel's ages (floor(q + 0.5)); any other pixel restarts
+ * from the frame, (x, var_init, 1) for both models.  The update then runs on
+ * that model and writes the mask (and bg, codes) of the frame and the new
+ * model to `dst`.  shape.T must be 1 (one call per frame); frame, masks, bg
+ * and codes are H x W with shape.row_stride; the state planes are dense
+ * H x W; no plane of `dst` may overlap a plane of `src` (DSGM_E_ARG).  With
+ * ACC_F64 the results are bit-identical to a scalar FP64 evaluation in the
+ * stated order.
+ */
+int dsgm_forward_warped(const void* frame, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                        dsgm_acc acc, const dsgm_params* params /* host */,
+                        const double* inv_map /* host, 9 */, const dsgm_state* src /* host struct */,
+                        dsgm_state* dst /* host struct */, uint8_t* masks, void* bg,
+                        uint8_t* codes, hipStream_t stream);
+
 /* one instance of a batch: its own sizes, strides, frames, state and outputs */
 typedef struct {
   dsgm_shape shape;

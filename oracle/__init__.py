@@ -82,6 +82,9 @@ def lib():
         _lib.orc_jvp.argtypes = ([ctypes.c_int64, ctypes.c_int64] + [dp] * 11 +
                                  [ctypes.c_double, dp, dp, ctypes.c_int])
         _lib.orc_max_threads.restype = ctypes.c_int
+        _lib.orc_warp_state.argtypes = [ctypes.c_int64, ctypes.c_int64] + [dp] * 9 + \
+            [dp] * 6 + [ctypes.c_int]
+        _lib.orc_warp_state.restype = ctypes.c_int
         _lib.orc_gauss_weights.argtypes = [ctypes.c_int32, ctypes.c_double, dp]
         _lib.orc_gauss_weights.restype = ctypes.c_int
         _lib.orc_preprocess.argtypes = ([ctypes.c_int64] * 3 + [dp, dp, ctypes.c_int32, dp,
@@ -229,4 +232,28 @@ def preprocess(frames, weights=None, median: bool = True, nthreads: int = 0) -> 
                               int(nthreads))
     if rc != 0:
         raise ValueError(f"orc_preprocess failed ({rc})")
+    return out
+
+
+# ------------------------------------------------------------ motion compensation
+def warp_state(state: dict, frame, inv_map, params: Params, H: int, W: int,
+               nthreads: int = 0) -> dict:
+    """The model after motion compensation (dsgm_oracle.c, orc_warp_state):
+    `inv_map` (3 x 3) takes a current pixel (column, row, 1) to its position in
+    the previous frame; bilinear means and variances, nearest ages, uncovered
+    pixels restarted from `frame` (H*W values)."""
+    N = H * W
+    mA, vA, aA, mC, vC, aC = _state_arrays(state, N)
+    m = np.ascontiguousarray(inv_map, dtype=np.float64).reshape(9)
+    x = _f64(frame, (N,))
+    out = {k: np.empty(N, np.float64) for k in ("mean_a", "var_a", "mean_c", "var_c")}
+    out["age_a"] = np.empty(N, np.int32)
+    out["age_c"] = np.empty(N, np.int32)
+    cp = _cp(params)
+    rc = lib().orc_warp_state(H, W, _ptr(m), _ptr(x), _ptr(mA), _ptr(vA), _ptr(aA), _ptr(mC),
+                              _ptr(vC), _ptr(aC), ctypes.byref(cp), _ptr(out["mean_a"]),
+                              _ptr(out["var_a"]), _ptr(out["age_a"]), _ptr(out["mean_c"]),
+                              _ptr(out["var_c"]), _ptr(out["age_c"]), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"orc_warp_state failed ({rc})")
     return out

@@ -374,3 +374,76 @@ int orc_jvp(int64_t T, int64_t N, const double* frames, const double* mean_a0,
   }
   return 0;
 }
+
+/*
+ * Motion compensation of the model (Sec. 2.2: the update uses the previous
+ * mean, variance and age "after motion compensation"; Sec. 2.4: with a
+ * per-pixel model the homography of the camera motion maps the model values to
+ * the pixels they now belong to).  The homography itself (KLT features and
+ * RANSAC in the paper) is an input: `map` (row-major 3 x 3) takes a pixel
+ * (c, y) of the current frame to its position in the previous one,
+ *   den = (map[6]*c + map[7]*y) + map[8],
+ *   qx  = ((map[0]*c + map[1]*y) + map[2]) / den,  qy likewise with map[3..5].
+ * Readings: a pixel is covered when den > 0 and (qx, qy) lies in
+ * [0, W-1] x [0, H-1]; its means and variances are the bilinear blend of the
+ * four surrounding pixels, weights (1-fx)(1-fy), fx(1-fy), (1-fx)fy, fx*fy with
+ * fx = qx - floor(qx), fy likewise, summed in that order (a neighbour index
+ * past the last row or column is clamped; its weight is then 0); its ages are
+ * the nearest pixel's, floor(q + 0.5), clamped.  An uncovered pixel has no
+ * history: both of its models start from the current intensity x, as in a
+ * state initialised from a frame, (x, var_init, 1).  src and dst are distinct
+ * H x W planes; `frame` is the current frame (H x W).
+ */
+int orc_warp_state(int64_t H, int64_t W, const double* map, const double* frame,
+                   const double* mean_a, const double* var_a, const int32_t* age_a,
+                   const double* mean_c, const double* var_c, const int32_t* age_c,
+                   const orc_params* p, double* o_mean_a, double* o_var_a, int32_t* o_age_a,
+                   double* o_mean_c, double* o_var_c, int32_t* o_age_c, int nthreads) {
+  int64_t y;
+  if (orc_check(p) || H < 0 || W < 0 || !map) return -1;
+  if (H == 0 || W == 0) return 0;
+  if (!frame || !mean_a || !var_a || !age_a || !mean_c || !var_c || !age_c || !o_mean_a ||
+      !o_var_a || !o_age_a || !o_mean_c || !o_var_c || !o_age_c)
+    return -1;
+  orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+  for (y = 0; y < H; ++y) {
+    int64_t c;
+    for (c = 0; c < W; ++c) {
+      const int64_t i = y * W + c;
+      const double xd = (double)c, yd = (double)y;
+      const double den = (map[6] * xd + map[7] * yd) + map[8];
+      const double qx = ((map[0] * xd + map[1] * yd) + map[2]) / den;
+      const double qy = ((map[3] * xd + map[4] * yd) + map[5]) / den;
+      if (!(den > 0.0) || !(qx >= 0.0) || !(qx <= (double)(W - 1)) || !(qy >= 0.0) ||
+          !(qy <= (double)(H - 1))) {
+        o_mean_a[i] = frame[i];
+        o_mean_c[i] = frame[i];
+        o_var_a[i] = p->var_init;
+        o_var_c[i] = p->var_init;
+        o_age_a[i] = 1;
+        o_age_c[i] = 1;
+        continue;
+      }
+      {
+        const double fx0 = floor(qx), fy0 = floor(qy);
+        const double fx = qx - fx0, fy = qy - fy0;
+        const int64_t x0 = (int64_t)fx0, y0 = (int64_t)fy0;
+        const int64_t x1 = x0 + 1 < W ? x0 + 1 : W - 1, y1 = y0 + 1 < H ? y0 + 1 : H - 1;
+        const double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy);
+        const double w01 = (1.0 - fx) * fy, w11 = fx * fy;
+        const int64_t i00 = y0 * W + x0, i10 = y0 * W + x1, i01 = y1 * W + x0, i11 = y1 * W + x1;
+        int64_t xn = (int64_t)floor(qx + 0.5), yn = (int64_t)floor(qy + 0.5);
+        if (xn > W - 1) xn = W - 1;
+        if (yn > H - 1) yn = H - 1;
+        o_mean_a[i] = ((w00 * mean_a[i00] + w10 * mean_a[i10]) + w01 * mean_a[i01]) + w11 * mean_a[i11];
+        o_var_a[i] = ((w00 * var_a[i00] + w10 * var_a[i10]) + w01 * var_a[i01]) + w11 * var_a[i11];
+        o_mean_c[i] = ((w00 * mean_c[i00] + w10 * mean_c[i10]) + w01 * mean_c[i01]) + w11 * mean_c[i11];
+        o_var_c[i] = ((w00 * var_c[i00] + w10 * var_c[i10]) + w01 * var_c[i01]) + w11 * var_c[i11];
+        o_age_a[i] = age_a[yn * W + xn];
+        o_age_c[i] = age_c[yn * W + xn];
+      }
+    }
+  }
+  return 0;
+}

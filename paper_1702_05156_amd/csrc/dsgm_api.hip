@@ -435,6 +435,82 @@ int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape
   return ok();
 }
 
+int dsgm_forward_warped(const void* frame, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                        dsgm_acc acc, const dsgm_params* params, const double* inv_map,
+                        const dsgm_state* src, dsgm_state* dst, uint8_t* masks, void* bg,
+                        uint8_t* codes, hipStream_t stream) {
+  int rc;
+  if ((rc = check_types(in_dtype, acc))) return rc;
+  if ((rc = check_params(params))) return rc;
+  if (!inv_map) return fail(DSGM_E_ARG, "inv_map is NULL");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(inv_map[i])) return fail(DSGM_E_ARG, "inv_map[%d] is not finite", i);
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
+  if ((rc = check_shape(shape, ie > oe ? ie : oe))) return rc;
+  if (shape.T != 1) return fail(DSGM_E_SHAPE, "T = %lld, need one frame per call",
+                                (long long)shape.T);
+  if (!src || !dst) return fail(DSGM_E_ARG, "src or dst is NULL");
+  const int64_t px = shape.H * shape.W;
+  if (px == 0) return ok();
+  if (!frame) return fail(DSGM_E_ARG, "frame is NULL");
+  if (!masks) return fail(DSGM_E_ARG, "masks is NULL");
+  const void* sp[6] = {src->mean_a, src->var_a, src->mean_c, src->var_c, src->age_a, src->age_c};
+  void* dp[6] = {dst->mean_a, dst->var_a, dst->mean_c, dst->var_c, dst->age_a, dst->age_c};
+  const size_t pe[6] = {ae, ae, ae, ae, 1, 1};
+  for (int i = 0; i < 6; ++i) {
+    if (!sp[i] || !dp[i]) return fail(DSGM_E_ARG, "a state plane is NULL");
+    if (!aligned(sp[i], pe[i]) || !aligned(dp[i], pe[i]))
+      return fail(DSGM_E_ALIGN, "state plane %d is not aligned to %zu bytes", i, pe[i]);
+  }
+  // the gathers read src while dst is written: no dst plane may overlap a src plane
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      const uintptr_t d0 = reinterpret_cast<uintptr_t>(dp[i]), d1 = d0 + size_t(px) * pe[i];
+      const uintptr_t s0 = reinterpret_cast<uintptr_t>(sp[j]), s1 = s0 + size_t(px) * pe[j];
+      if (d0 < s1 && s0 < d1) return fail(DSGM_E_ARG, "dst plane %d overlaps src plane %d", i, j);
+    }
+  const void* ptrs[4] = {frame, masks, bg, codes};
+  const size_t elem[4] = {ie, 1, oe, 1};
+  for (int i = 0; i < 4; ++i)
+    if (ptrs[i] && !aligned(ptrs[i], elem[i]))
+      return fail(DSGM_E_ALIGN, "pointer argument %d is not aligned to %zu bytes", i, elem[i]);
+
+  dsgm::WarpArgs a;
+  memset(&a, 0, sizeof(a));
+  a.frame = frame;
+  a.masks = masks;
+  a.bg = bg;
+  a.codes = codes;
+  a.src_mean_a = src->mean_a;
+  a.src_var_a = src->var_a;
+  a.src_mean_c = src->mean_c;
+  a.src_var_c = src->var_c;
+  a.src_age_a = src->age_a;
+  a.src_age_c = src->age_c;
+  a.dst_mean_a = dst->mean_a;
+  a.dst_var_a = dst->var_a;
+  a.dst_mean_c = dst->mean_c;
+  a.dst_var_c = dst->var_c;
+  a.dst_age_a = dst->age_a;
+  a.dst_age_c = dst->age_c;
+  a.H = shape.H;
+  a.W = shape.W;
+  a.row_stride = shape.row_stride;
+  for (int i = 0; i < 9; ++i) a.map[i] = inv_map[i];
+  a.theta_s = params->theta_s;
+  a.theta_d = params->theta_d;
+  a.var_init = params->var_init;
+  a.var_floor = params->var_floor;
+  a.mask_floor = params->mask_floor;
+  a.age_max = params->age_max;
+  a.weight_rule = params->weight_rule;
+  a.mask_rule = params->mask_rule;
+  if ((px + 255) / 256 >= (int64_t(1) << 31)) return fail(DSGM_E_SHAPE, "frame too large");
+  hipError_t e = dsgm::launch_warp(a, in_dtype, acc, stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_forward_warped launch");
+  return ok();
+}
+
 size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc) {
   if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32) return 0;
   if (shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;

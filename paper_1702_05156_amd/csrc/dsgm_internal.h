@@ -115,6 +115,33 @@ struct PreArgs {
 hipError_t launch_pre(const PreArgs& a, int in_dtype, int acc, int rg, bool median,
                       hipStream_t stream);
 
+// Arguments of one frame of the update on the motion-compensated model
+// (dsgm_warp.hip).
+struct WarpArgs {
+  const void* frame;
+  uint8_t* masks;
+  void* bg;        // NULL: none
+  uint8_t* codes;  // NULL: none
+  const void* src_mean_a;
+  const void* src_var_a;
+  const void* src_mean_c;
+  const void* src_var_c;
+  const uint8_t* src_age_a;
+  const uint8_t* src_age_c;
+  void* dst_mean_a;
+  void* dst_var_a;
+  void* dst_mean_c;
+  void* dst_var_c;
+  uint8_t* dst_age_a;
+  uint8_t* dst_age_c;
+  int64_t H, W, row_stride;
+  double map[9];  // current pixel (column, row, 1) -> previous frame, row-major
+  double theta_s, theta_d, var_init, var_floor, mask_floor;
+  int32_t age_max, weight_rule, mask_rule;
+};
+
+hipError_t launch_warp(const WarpArgs& a, int in_dtype, int acc, hipStream_t stream);
+
 // Variant flags of the forward kernels (see dsgm_fwd_impl.h).
 enum : int { FWD_BG = 1, FWD_CODES = 2, FWD_CKPT = 4, FWD_PRINTED = 8 };
 

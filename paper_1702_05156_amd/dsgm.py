@@ -104,6 +104,9 @@ def _load():
     lib.dsgm_forward_filtered.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params),
                                           ctypes.POINTER(Filter), ctypes.POINTER(_State), vp, vp,
                                           vp, vp, vp]
+    lib.dsgm_forward_warped.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_State),
+                                        ctypes.POINTER(_State), vp, vp, vp, vp]
     lib.dsgm_ckpt_bytes.argtypes = [Shape, i32, i32]
     lib.dsgm_ckpt_bytes.restype = ctypes.c_size_t
     lib.dsgm_workspace_bytes.argtypes = [Shape, i32]
@@ -122,7 +125,8 @@ def _load():
     lib.dsgm_set_launch.argtypes = [i32, i32]
     for f in ("dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
               "dsgm_backward", "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_version",
-              "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered"):
+              "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
+              "dsgm_forward_warped"):
         getattr(lib, f).restype = ctypes.c_int
     del i64
     return lib
@@ -134,7 +138,8 @@ lib = _load()
 EXPORTS = ["dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
            "dsgm_ckpt_bytes", "dsgm_workspace_bytes", "dsgm_backward", "dsgm_batch_plan_bytes",
            "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_status_string", "dsgm_last_error",
-           "dsgm_version", "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered"]
+           "dsgm_version", "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
+           "dsgm_forward_warped"]
 
 
 def _check(fn: str, rc: int):
@@ -308,6 +313,33 @@ def dsgm_forward_filtered(frames: torch.Tensor, state: State, params: Params, fi
                                      ctypes.byref(params), ctypes.byref(filt), ctypes.byref(cs),
                                      _ptr(masks), _ptr(bg), _ptr(filtered), _ptr(codes),
                                      _stream()))
+
+
+def dsgm_forward_warped(frame: torch.Tensor, src: State, dst: State, params: Params, inv_map,
+                        masks: torch.Tensor, bg: torch.Tensor | None = None,
+                        codes: torch.Tensor | None = None, acc=None) -> None:
+    """One frame (H x W) of the update on the model in ``src`` mapped through the
+    3 x 3 ``inv_map`` (current pixel -> previous frame); the new model goes to
+    ``dst`` (distinct planes), masks/bg/codes are H x W like the frame."""
+    if frame.dtype not in _IN_DTYPES:
+        raise TypeError(f"frame dtype {frame.dtype} not supported")
+    if frame.dim() != 2:
+        raise ValueError("frame must be H x W")
+    H, W = frame.shape
+    f3 = frame.unsqueeze(0)
+    sh = _frames_shape(f3)
+    acc = _resolve_acc(src, acc)
+    if _resolve_acc(dst, acc) != acc:
+        raise ValueError("src and dst must have the same state type")
+    _same_layout("masks", masks.unsqueeze(0), f3, torch.uint8)
+    _same_layout("bg", None if bg is None else bg.unsqueeze(0), f3, ACC_TORCH[acc])
+    _same_layout("codes", None if codes is None else codes.unsqueeze(0), f3, torch.uint8)
+    m = (ctypes.c_double * 9)(*[float(v) for v in torch.as_tensor(inv_map, dtype=torch.float64).reshape(9).tolist()])
+    cs, cd = _cstate(src, H, W), _cstate(dst, H, W)
+    _check("dsgm_forward_warped",
+           lib.dsgm_forward_warped(_ptr(frame), _IN_DTYPES[frame.dtype], sh, acc,
+                                   ctypes.byref(params), m, ctypes.byref(cs), ctypes.byref(cd),
+                                   _ptr(masks), _ptr(bg), _ptr(codes), _stream()))
 
 
 def dsgm_workspace_bytes(T: int, H: int, W: int, acc: int) -> int:

@@ -215,3 +215,28 @@ def test_filtered_forward_validation():
     for n, s in [(4, 1.0), (9, 1.0), (5, 0.0)]:
         with pytest.raises(dsgm.DSGMError):
             dsgm.dsgm_gauss_weights(n, s)
+
+
+def test_warped_forward_validation():
+    """dsgm_forward_warped rejects T != 1, overlapping src/dst planes and a
+    non-finite map before any HIP call."""
+    p = dsgm.dsgm_params_default(2.0)
+    m = (ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    base = 1 << 20
+    src = dsgm._State(base, base + 4096, base + 8192, base + 12288, base + 16384, base + 16640)
+    dst = dsgm._State(base + 32768, base + 36864, base + 40960, base + 45056, base + 49152,
+                      base + 49408)
+    sh = dsgm.Shape(1, 8, 8, 8, 64)
+    rc = dsgm.lib.dsgm_forward_warped(base, 0, dsgm.Shape(2, 8, 8, 8, 64), 0, ctypes.byref(p), m,
+                                      ctypes.byref(src), ctypes.byref(dst), base, None, None, None)
+    assert rc == -2
+    rc = dsgm.lib.dsgm_forward_warped(base, 0, sh, 0, ctypes.byref(p), m, ctypes.byref(src),
+                                      ctypes.byref(src), base, None, None, None)
+    assert rc == E_ARG
+    bad = (ctypes.c_double * 9)(1, 0, float("nan"), 0, 1, 0, 0, 0, 1)
+    rc = dsgm.lib.dsgm_forward_warped(base, 0, sh, 0, ctypes.byref(p), bad, ctypes.byref(src),
+                                      ctypes.byref(dst), base, None, None, None)
+    assert rc == E_ARG
+    rc = dsgm.lib.dsgm_forward_warped(base, 0, sh, 0, ctypes.byref(p), None, ctypes.byref(src),
+                                      ctypes.byref(dst), base, None, None, None)
+    assert rc == E_ARG

@@ -112,3 +112,39 @@ def test_filtered_fp32_within_tolerance(in_dtype):
     ref = oracle.forward(xf, st0, G.oracle_params(p), margins=True)
     div = _certify_fp32(G.flat(out["codes"]), ref, tol_margin=1e-5)
     assert div.mean() <= 1e-3, div.mean()
+
+
+@pytest.mark.slow
+def test_full_size_filtered_f64_sampled_bit_exact():
+    """1920x2560x500, FP64, 5-tap Gaussian (sigma 1) and 3x3 median fused, masks
+    only -- the launch the benchmark times.  A filtered pixel depends on the raw
+    frame within 3 rows and columns, so the oracle filters a 7x7 crop around each
+    sampled pixel (cut at the frame edges, where both clamp alike) and runs the
+    update on the crop's centre."""
+    T, H, W, seed = 500, 1920, 2560, 1
+    p = dsgm.dsgm_params_default(2.0)
+    filt = dsgm.gauss_filter(5, 1.0, True)
+    fr, st = G.device_case(seed, T, H, W)
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    dsgm.dsgm_forward_filtered(fr, st, p, filt, masks)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    pix = np.unique(np.concatenate([rng.choice(H * W, 256, replace=False),
+                                    [0, 1, W - 1, W, H * W - W, H * W - 1, 2 * W + 2]]))
+    w = oracle.gauss_weights(5, 1.0)
+    xf = np.empty((T, pix.size))
+    for k, q in enumerate(pix):
+        y, x = divmod(int(q), W)
+        ys = np.arange(max(0, y - 3), min(H, y + 4))
+        xs = np.arange(max(0, x - 3), min(W, x + 4))
+        crop_pix = (ys[:, None] * W + xs[None, :]).ravel()
+        raw = synth.frames(seed, T, H, W, "f64", pix=crop_pix).reshape(T, ys.size, xs.size)
+        xf[:, k] = oracle.preprocess(raw, w)[:, y - ys[0], x - xs[0]]
+    _, st0 = G.host_case(seed, 1, H, W, pix=pix)
+    ref = oracle.forward(xf, st0, G.oracle_params(p), bg=False, codes=False)
+    pix_t = torch.as_tensor(pix, device="cuda")
+    G.assert_bit_exact("masks", masks.view(T, H * W)[:, pix_t].cpu().numpy(), ref["masks"])
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k][pix], ref[k])
+    del fr, masks
