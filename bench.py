@@ -2,7 +2,7 @@
 """Throughput of the DSGM hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--legs main,mixed,video,filtered,warped,attainable,adjoint,batched,largest]
+                    [--legs main,mixed,video,filtered,warped,grid,attainable,adjoint,batched,largest]
                     [--no-cpu-baseline]
 
 Main workload (the `value`): the plain method in FP64, one instance of
@@ -24,6 +24,7 @@ Secondary legs, reported under "legs" (same timing method):
            median) fused into the forward, FP64 and BF16/FP32
   warped   motion-compensated update: 100 frames, one launch per frame, each with
            its own camera homography (the model is gathered through it), FP64
+  grid     Yi et al.'s grid model (4x4-pixel blocks) on the main workload's frames
   attainable  the same bytes as the forward and backward kernels moved by kernels
            with no model arithmetic: the attainable HBM rate of each access pattern
   adjoint  FP32 frames and state, bg on, checkpoints every 32 frames, upstream
@@ -285,6 +286,27 @@ def leg_warped(args, dsgm, sdev, torch):
     return out
 
 
+def leg_grid(args, dsgm, sdev, torch):
+    """Yi et al.'s grid model, blocks of 4 x 4 pixels, on the main workload's
+    FP64 frames (1920x2560x500, seed 1) from a random block state; element =
+    one pixel-frame (its mask bit), as for the pixel model."""
+    T, H, W, seed, b = 500, 1920, 2560, 1, 4
+    p = dsgm.dsgm_params_default(2.0)
+    stream = torch.cuda.current_stream()
+    fr = sdev.frames(seed, T, H, W, torch.float64)
+    st = dsgm.State(*sdev.state(seed, H // b, W // b, torch.float64))
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    steps = max(3, args.steps // 2)
+    ms, kk = timed(lambda: dsgm.dsgm_forward_grid(fr, st, p, b, masks), steps, 1, stream)
+    elems = T * H * W
+    out = {"workload": "1920x2560x500 fp64, 4x4-pixel blocks, masks only",
+           "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+           "roofline": roof(elems * 9 + (H // b) * (W // b) * 68, float(sum(kk) / len(kk)))}
+    del fr, st, masks
+    torch.cuda.empty_cache()
+    return out
+
+
 def leg_attainable(args, dsgm, sdev, torch):
     """Attainable HBM rate of each kernel's access pattern: kernels that move the
     same bytes in the same order, widths and cache hints as the forward and
@@ -540,7 +562,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--legs",
-                    default="main,mixed,video,filtered,warped,attainable,adjoint,batched,largest")
+                    default="main,mixed,video,filtered,warped,grid,attainable,adjoint,batched,largest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
@@ -597,7 +619,7 @@ def main():
     out_legs = {}
     progress(f"main leg done: {value / 1e9:.1f} G elements/s")
     for name, fn in (("mixed", leg_mixed), ("video", leg_video), ("filtered", leg_filtered),
-                     ("warped", leg_warped),
+                     ("warped", leg_warped), ("grid", leg_grid),
                      ("attainable", leg_attainable), ("adjoint", leg_adjoint),
                      ("batched", leg_batched), ("largest", leg_largest)):
         if name in legs:

@@ -269,6 +269,26 @@ int dsgm_forward_warped(const void* frame, dsgm_in_dtype in_dtype, dsgm_shape sh
                         dsgm_state* dst /* host struct */, uint8_t* masks, void* bg,
                         uint8_t* codes, hipStream_t stream);
 
+/*
+ * Yi et al.'s grid model, which Sec. 2.2 describes and the paper reduces to
+ * one pixel: one dual model per block of b x b pixels (b = 1, 2 or 4; edge
+ * blocks keep the pixels that exist).  Per frame and block the tests, the
+ * blend and the reset use the block mean M = (row-major sum from 0) / |G|,
+ * and the matched model's variance term is the largest squared distance of
+ * the updated mean from the block's intensities; each pixel's mask bit uses
+ * the block's apparent model.  b = 1 is exactly dsgm_forward.
+ *   state    Hb x Wb planes (Hb = ceil(H/b), Wb = ceil(W/b)), updated in place
+ *   masks    T x H x W, strided like the frames
+ *   bg       NULL or T x Hb x Wb dense, array type: the block's mean_A after
+ *            each frame
+ *   codes    NULL or T x Hb x Wb dense (CODE_* bits without CODE_FG)
+ * b outside {1, 2, 4} returns DSGM_E_UNSUPPORTED.
+ */
+int dsgm_forward_grid(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
+                      const dsgm_params* params /* host */, int32_t b,
+                      dsgm_state* state /* host struct */, uint8_t* masks, void* bg,
+                      uint8_t* codes, hipStream_t stream);
+
 /* one instance of a batch: its own sizes, strides, frames, state and outputs */
 typedef struct {
   dsgm_shape shape;

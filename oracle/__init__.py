@@ -85,6 +85,9 @@ def lib():
         _lib.orc_warp_state.argtypes = [ctypes.c_int64, ctypes.c_int64] + [dp] * 9 + \
             [dp] * 6 + [ctypes.c_int]
         _lib.orc_warp_state.restype = ctypes.c_int
+        _lib.orc_forward_grid.argtypes = ([ctypes.c_int64] * 3 + [ctypes.c_int32] + [dp] * 10 +
+                                          [ctypes.c_int])
+        _lib.orc_forward_grid.restype = ctypes.c_int
         _lib.orc_gauss_weights.argtypes = [ctypes.c_int32, ctypes.c_double, dp]
         _lib.orc_gauss_weights.restype = ctypes.c_int
         _lib.orc_preprocess.argtypes = ([ctypes.c_int64] * 3 + [dp, dp, ctypes.c_int32, dp,
@@ -257,3 +260,28 @@ def warp_state(state: dict, frame, inv_map, params: Params, H: int, W: int,
     if rc != 0:
         raise ValueError(f"orc_warp_state failed ({rc})")
     return out
+
+
+# --------------------------------------------------------------- grid model
+def forward_grid(frames, state: dict, params: Params, block: int, *, codes=True,
+                 nthreads: int = 0) -> dict:
+    """Yi et al.'s grid model (blocks of block x block pixels; dsgm_oracle.c,
+    orc_forward_grid).  frames (T, H, W); state arrays hold Hb x Wb blocks.
+    Returns the final state, masks (T, H, W) and codes (T, Hb*Wb)."""
+    x = np.ascontiguousarray(frames, dtype=np.float64)
+    T, H, W = x.shape
+    Hb, Wb = -(-H // block), -(-W // block)
+    mA, vA, aA, mC, vC, aC = _state_arrays(state, Hb * Wb)
+    masks = np.empty((T, H, W), np.uint8)
+    cd = np.empty((T, Hb * Wb), np.uint8) if codes else None
+    cp = _cp(params)
+    rc = lib().orc_forward_grid(T, H, W, int(block), _ptr(x), _ptr(mA), _ptr(vA), _ptr(aA),
+                                _ptr(mC), _ptr(vC), _ptr(aC), ctypes.byref(cp), _ptr(masks),
+                                _ptr(cd), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"orc_forward_grid failed ({rc})")
+    res = {"mean_a": mA, "var_a": vA, "age_a": aA, "mean_c": mC, "var_c": vC, "age_c": aC,
+           "masks": masks}
+    if codes:
+        res["codes"] = cd
+    return res

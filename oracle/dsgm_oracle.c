@@ -447,3 +447,92 @@ int orc_warp_state(int64_t H, int64_t W, const double* map, const double* frame,
   }
   return 0;
 }
+
+/*
+ * Yi et al.'s grid model, which the paper describes (Sec. 2.2) and reduces to
+ * one pixel per grid: the frame is cut into blocks G of b x b pixels (blocks on
+ * the right and bottom edges keep the pixels that exist), one dual model per
+ * block.  Per frame and block:
+ *   M = (sum of the block's intensities, row-major from 0) / |G|
+ *   the match tests, reset and swap of Sec. 2.3 use M for the intensity;
+ *   the matched model's mean is blended with M; its V is the largest squared
+ *   distance of the updated mean from the block's intensities,
+ *   V = max over j in G of (mean' - I_j)^2 (instead of (mean' - M)^2);
+ *   a pixel is background iff (mean_A - I_j)^2 <= theta_d * max(mask floor, ref),
+ *   ref = var_A or I_j (the per-pixel rule of the appendix with the block's A).
+ * With b = 1 this is exactly orc_forward.  State arrays hold Hb x Wb blocks
+ * (Hb = ceil(H/b), Wb = ceil(W/b)); frames and masks are T x H x W; codes
+ * (optional) T x Hb x Wb.
+ */
+int orc_forward_grid(int64_t T, int64_t H, int64_t W, int32_t b, const double* frames,
+                     double* mean_a, double* var_a, int32_t* age_a, double* mean_c, double* var_c,
+                     int32_t* age_c, const orc_params* p, uint8_t* masks, uint8_t* codes,
+                     int nthreads) {
+  int64_t Hb, Wb, nb, k;
+  if (orc_check(p) || T < 0 || H < 0 || W < 0 || b < 1) return -1;
+  if (T == 0 || H == 0 || W == 0) return 0;
+  if (!frames || !mean_a || !var_a || !age_a || !mean_c || !var_c || !age_c || !masks) return -1;
+  Hb = (H + b - 1) / b;
+  Wb = (W + b - 1) / b;
+  nb = Hb * Wb;
+  orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+  for (k = 0; k < nb; ++k) {
+    const int64_t by = k / Wb, bx = k % Wb;
+    const int64_t y0 = by * b, x0 = bx * b;
+    const int64_t y1 = y0 + b < H ? y0 + b : H, x1 = x0 + b < W ? x0 + b : W;
+    const double n = (double)((y1 - y0) * (x1 - x0));
+    orc_model A = {mean_a[k], var_a[k], age_a[k]};
+    orc_model C = {mean_c[k], var_c[k], age_c[k]};
+    int64_t t, y, x;
+    for (t = 0; t < T; ++t) {
+      const double* f = frames + t * H * W;
+      double sum = 0.0, M;
+      int hit_a, hit_c;
+      uint8_t code = 0;
+      orc_model* U = NULL;
+      for (y = y0; y < y1; ++y)
+        for (x = x0; x < x1; ++x) sum += f[y * W + x];
+      M = sum / n;
+      hit_a = orc_sq(M - A.mean) < p->theta_s * orc_max(A.var, p->var_floor);
+      hit_c = !hit_a && orc_sq(M - C.mean) < p->theta_s * orc_max(C.var, p->var_floor);
+      if (hit_a) {
+        code |= ORC_HIT_A;
+        U = &A;
+      } else if (hit_c) {
+        code |= ORC_HIT_C;
+        U = &C;
+      } else {
+        code |= ORC_RESET;
+        orc_reset(&C, M, p);
+      }
+      if (U) {
+        const double w = orc_weight(U->age, p);
+        const double u = 1.0 - w;
+        const double mean = u * U->mean + w * M;
+        double V = 0.0;
+        for (y = y0; y < y1; ++y)
+          for (x = x0; x < x1; ++x) V = orc_max(V, orc_sq(mean - f[y * W + x]));
+        U->var = u * U->var + w * V;
+        U->mean = mean;
+        U->age = U->age < p->age_max ? U->age + 1 : p->age_max;
+      }
+      if (C.age > A.age) {
+        code |= ORC_SWAP;
+        A = C;
+        orc_reset(&C, M, p);
+      }
+      for (y = y0; y < y1; ++y)
+        for (x = x0; x < x1; ++x) {
+          const double I = f[y * W + x];
+          const double ref = p->mask_rule == ORC_MASK_PRINTED ? I : A.var;
+          const int fg = !(orc_sq(A.mean - I) <= p->theta_d * orc_max(p->mask_floor, ref));
+          masks[t * H * W + y * W + x] = fg ? 255 : 0;
+        }
+      if (codes) codes[t * nb + k] = code;
+    }
+    mean_a[k] = A.mean; var_a[k] = A.var; age_a[k] = A.age;
+    mean_c[k] = C.mean; var_c[k] = C.var; age_c[k] = C.age;
+  }
+  return 0;
+}

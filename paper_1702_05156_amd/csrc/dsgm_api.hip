@@ -511,6 +511,62 @@ int dsgm_forward_warped(const void* frame, dsgm_in_dtype in_dtype, dsgm_shape sh
   return ok();
 }
 
+int dsgm_forward_grid(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
+                      const dsgm_params* params, int32_t b, dsgm_state* state, uint8_t* masks,
+                      void* bg, uint8_t* codes, hipStream_t stream) {
+  int rc;
+  if ((rc = check_types(in_dtype, acc))) return rc;
+  if ((rc = check_params(params))) return rc;
+  if (b != 1 && b != 2 && b != 4) return fail(DSGM_E_UNSUPPORTED, "block size %d (1, 2 or 4)", b);
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
+  if ((rc = check_shape(shape, ie))) return rc;
+  if (!state) return fail(DSGM_E_ARG, "state is NULL");
+  if (shape.H * shape.W == 0 || shape.T == 0) return ok();
+  if (!frames) return fail(DSGM_E_ARG, "frames is NULL");
+  if (!masks) return fail(DSGM_E_ARG, "masks is NULL");
+  if (!state->mean_a || !state->var_a || !state->mean_c || !state->var_c || !state->age_a ||
+      !state->age_c)
+    return fail(DSGM_E_ARG, "a state plane is NULL");
+  const void* ptrs[8] = {frames, masks, bg, codes, state->mean_a, state->var_a, state->mean_c,
+                         state->var_c};
+  const size_t elem[8] = {ie, 1, oe, 1, ae, ae, ae, ae};
+  for (int i = 0; i < 8; ++i)
+    if (ptrs[i] && !aligned(ptrs[i], elem[i]))
+      return fail(DSGM_E_ALIGN, "pointer argument %d is not aligned to %zu bytes", i, elem[i]);
+  dsgm::GridArgs a;
+  memset(&a, 0, sizeof(a));
+  a.frames = frames;
+  a.masks = masks;
+  a.bg = bg;
+  a.codes = codes;
+  a.mean_a = state->mean_a;
+  a.var_a = state->var_a;
+  a.mean_c = state->mean_c;
+  a.var_c = state->var_c;
+  a.age_a = state->age_a;
+  a.age_c = state->age_c;
+  a.T = shape.T;
+  a.H = shape.H;
+  a.W = shape.W;
+  a.row_stride = shape.row_stride;
+  a.frame_stride = shape.frame_stride;
+  a.Hb = (shape.H + b - 1) / b;
+  a.Wb = (shape.W + b - 1) / b;
+  a.vec_ok = shape.row_stride % b == 0 && (shape.T <= 1 || shape.frame_stride % b == 0) &&
+             aligned(frames, ie * b) && aligned(masks, size_t(b));
+  a.theta_s = params->theta_s;
+  a.theta_d = params->theta_d;
+  a.var_init = params->var_init;
+  a.var_floor = params->var_floor;
+  a.mask_floor = params->mask_floor;
+  a.age_max = params->age_max;
+  a.weight_rule = params->weight_rule;
+  a.mask_rule = params->mask_rule;
+  hipError_t e = dsgm::launch_grid(a, in_dtype, acc, b, stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_forward_grid launch");
+  return ok();
+}
+
 size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc) {
   if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32) return 0;
   if (shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;

@@ -142,6 +142,26 @@ struct WarpArgs {
 
 hipError_t launch_warp(const WarpArgs& a, int in_dtype, int acc, hipStream_t stream);
 
+// Arguments of the grid-model forward (dsgm_grid.hip).
+struct GridArgs {
+  const void* frames;
+  uint8_t* masks;  // T x H x W, strided like the frames
+  void* bg;        // NULL or T x Hb x Wb dense: mean_A of each block after each frame
+  uint8_t* codes;  // NULL or T x Hb x Wb dense
+  void* mean_a;    // Hb x Wb planes
+  void* var_a;
+  void* mean_c;
+  void* var_c;
+  uint8_t* age_a;
+  uint8_t* age_c;
+  int64_t T, H, W, row_stride, frame_stride, Hb, Wb;
+  int32_t vec_ok;  // whole blocks may use one vector access per row
+  double theta_s, theta_d, var_init, var_floor, mask_floor;
+  int32_t age_max, weight_rule, mask_rule;
+};
+
+hipError_t launch_grid(const GridArgs& a, int in_dtype, int acc, int b, hipStream_t stream);
+
 // Variant flags of the forward kernels (see dsgm_fwd_impl.h).
 enum : int { FWD_BG = 1, FWD_CODES = 2, FWD_CKPT = 4, FWD_PRINTED = 8 };
 

@@ -107,6 +107,8 @@ def _load():
     lib.dsgm_forward_warped.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_State),
                                         ctypes.POINTER(_State), vp, vp, vp, vp]
+    lib.dsgm_forward_grid.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params), i32,
+                                      ctypes.POINTER(_State), vp, vp, vp, vp]
     lib.dsgm_ckpt_bytes.argtypes = [Shape, i32, i32]
     lib.dsgm_ckpt_bytes.restype = ctypes.c_size_t
     lib.dsgm_workspace_bytes.argtypes = [Shape, i32]
@@ -126,7 +128,7 @@ def _load():
     for f in ("dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
               "dsgm_backward", "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_version",
               "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
-              "dsgm_forward_warped"):
+              "dsgm_forward_warped", "dsgm_forward_grid"):
         getattr(lib, f).restype = ctypes.c_int
     del i64
     return lib
@@ -139,7 +141,7 @@ EXPORTS = ["dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
            "dsgm_ckpt_bytes", "dsgm_workspace_bytes", "dsgm_backward", "dsgm_batch_plan_bytes",
            "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_status_string", "dsgm_last_error",
            "dsgm_version", "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
-           "dsgm_forward_warped"]
+           "dsgm_forward_warped", "dsgm_forward_grid"]
 
 
 def _check(fn: str, rc: int):
@@ -340,6 +342,30 @@ def dsgm_forward_warped(frame: torch.Tensor, src: State, dst: State, params: Par
            lib.dsgm_forward_warped(_ptr(frame), _IN_DTYPES[frame.dtype], sh, acc,
                                    ctypes.byref(params), m, ctypes.byref(cs), ctypes.byref(cd),
                                    _ptr(masks), _ptr(bg), _ptr(codes), _stream()))
+
+
+def dsgm_forward_grid(frames: torch.Tensor, state: State, params: Params, block: int,
+                      masks: torch.Tensor, bg: torch.Tensor | None = None,
+                      codes: torch.Tensor | None = None, acc=None) -> None:
+    """Yi et al.'s grid model: one dual model per block x block pixels; ``state``
+    holds ceil(H/b) x ceil(W/b) planes; masks like the frames; bg and codes
+    (optional) dense T x Hb x Wb."""
+    if frames.dtype not in _IN_DTYPES:
+        raise TypeError(f"frames dtype {frames.dtype} not supported")
+    sh = _frames_shape(frames)
+    T, H, W = frames.shape
+    Hb, Wb = -(-H // block), -(-W // block)
+    acc = _resolve_acc(state, acc)
+    _same_layout("masks", masks, frames, torch.uint8)
+    for name, t, dt in (("bg", bg, ACC_TORCH[acc]), ("codes", codes, torch.uint8)):
+        if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous()
+                              or tuple(t.shape) != (T, Hb, Wb)):
+            raise ValueError(f"{name}: need a contiguous CUDA {dt} tensor of shape {(T, Hb, Wb)}")
+    cs = _cstate(state, Hb, Wb)
+    _check("dsgm_forward_grid",
+           lib.dsgm_forward_grid(_ptr(frames), _IN_DTYPES[frames.dtype], sh, acc,
+                                 ctypes.byref(params), int(block), ctypes.byref(cs), _ptr(masks),
+                                 _ptr(bg), _ptr(codes), _stream()))
 
 
 def dsgm_workspace_bytes(T: int, H: int, W: int, acc: int) -> int:

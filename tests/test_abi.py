@@ -240,3 +240,13 @@ def test_warped_forward_validation():
     rc = dsgm.lib.dsgm_forward_warped(base, 0, sh, 0, ctypes.byref(p), None, ctypes.byref(src),
                                       ctypes.byref(dst), base, None, None, None)
     assert rc == E_ARG
+
+
+def test_grid_forward_validation():
+    p = dsgm.dsgm_params_default(2.0)
+    st = dsgm._State(1 << 20, 1 << 21, 1 << 22, 1 << 23, 1 << 24, 1 << 25)
+    for b, want in [(3, -7), (8, -7), (0, -7)]:
+        rc = dsgm.lib.dsgm_forward_grid(1 << 20, 0, dsgm.Shape(2, 8, 8, 8, 64), 0,
+                                        ctypes.byref(p), b, ctypes.byref(st), 1 << 20, None, None,
+                                        None)
+        assert rc == want, (b, rc)
