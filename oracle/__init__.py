@@ -88,6 +88,8 @@ def lib():
         _lib.orc_forward_grid.argtypes = ([ctypes.c_int64] * 3 + [ctypes.c_int32] + [dp] * 10 +
                                           [ctypes.c_int])
         _lib.orc_forward_grid.restype = ctypes.c_int
+        _lib.orc_forward_u8.argtypes = [ctypes.c_int64, ctypes.c_int64] + [dp] * 10 + [ctypes.c_int]
+        _lib.orc_forward_u8.restype = ctypes.c_int
         _lib.orc_gauss_weights.argtypes = [ctypes.c_int32, ctypes.c_double, dp]
         _lib.orc_gauss_weights.restype = ctypes.c_int
         _lib.orc_preprocess.argtypes = ([ctypes.c_int64] * 3 + [dp, dp, ctypes.c_int32, dp,
@@ -280,6 +282,31 @@ def forward_grid(frames, state: dict, params: Params, block: int, *, codes=True,
                                 _ptr(cd), int(nthreads))
     if rc != 0:
         raise ValueError(f"orc_forward_grid failed ({rc})")
+    res = {"mean_a": mA, "var_a": vA, "age_a": aA, "mean_c": mC, "var_c": vC, "age_c": aC,
+           "masks": masks}
+    if codes:
+        res["codes"] = cd
+    return res
+
+
+# ------------------------------------------------------- 8-bit as-run model
+def forward_u8(frames, state: dict, params: Params, *, codes=True, nthreads: int = 0) -> dict:
+    """The appendix's 8-bit as-run model (dsgm_oracle.c, orc_forward_u8):
+    uint8 frames (T, N); state means/variances uint8, ages int."""
+    x = np.ascontiguousarray(frames, dtype=np.uint8)
+    T = x.shape[0]
+    N = int(np.prod(x.shape[1:])) if x.ndim > 1 else 0
+    x = x.reshape(T, N)
+    u8 = lambda k: np.ascontiguousarray(state[k], dtype=np.uint8).reshape(N).copy()
+    i32 = lambda k: np.ascontiguousarray(state[k], dtype=np.int32).reshape(N).copy()
+    mA, vA, mC, vC, aA, aC = u8("mean_a"), u8("var_a"), u8("mean_c"), u8("var_c"), i32("age_a"), i32("age_c")
+    masks = np.empty((T, N), np.uint8)
+    cd = np.empty((T, N), np.uint8) if codes else None
+    cp = _cp(params)
+    rc = lib().orc_forward_u8(T, N, _ptr(x), _ptr(mA), _ptr(vA), _ptr(aA), _ptr(mC), _ptr(vC),
+                              _ptr(aC), ctypes.byref(cp), _ptr(masks), _ptr(cd), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"orc_forward_u8 failed ({rc})")
     res = {"mean_a": mA, "var_a": vA, "age_a": aA, "mean_c": mC, "var_c": vC, "age_c": aC,
            "masks": masks}
     if codes:

@@ -118,8 +118,33 @@ static void orc_reset(orc_model* m, double x, const orc_params* p) {
  * margins (lhs - rhs of the A test, the C test and the background test) when
  * `margins` is not NULL.  Returns the decision code.
  */
+/* The appendix keeps means and variances in 8-bit images: every value written
+ * to one is converted to an integer (the fraction dropped), and here limited
+ * to [0, 255] (a conversion outside that range has no defined result). */
+static double orc_u8(double v) {
+  if (!(v > 0.0)) return 0.0;
+  if (v >= 255.0) return 255.0;
+  return trunc(v);
+}
+
+static void orc_quantize(orc_model* m) {
+  m->mean = orc_u8(m->mean);
+  m->var = orc_u8(m->var);
+}
+
+static uint8_t orc_step_q(orc_model* A, orc_model* C, double x, const orc_params* p, int forced,
+                          orc_tape* tp, double* margins, int quant);
+
 static uint8_t orc_step(orc_model* A, orc_model* C, double x, const orc_params* p, int forced,
                         orc_tape* tp, double* margins) {
+  return orc_step_q(A, C, x, p, forced, tp, margins, 0);
+}
+
+/* `quant`: the 8-bit as-run model of the appendix -- the matched model (or the
+ * reset candidate) is stored through orc_u8 before the swap test and the
+ * mask, which therefore see the stored values. */
+static uint8_t orc_step_q(orc_model* A, orc_model* C, double x, const orc_params* p, int forced,
+                          orc_tape* tp, double* margins, int quant) {
   uint8_t code = 0;
   double qa = orc_sq(x - A->mean);
   double ta = p->theta_s * orc_max(A->var, p->var_floor);
@@ -145,12 +170,17 @@ static uint8_t orc_step(orc_model* A, orc_model* C, double x, const orc_params* 
     code |= ORC_RESET;
     orc_reset(C, x, p);
   }
+  if (quant) {
+    orc_quantize(A);
+    orc_quantize(C);
+  }
 
   swap = (forced >= 0) ? ((forced & ORC_SWAP) != 0) : (C->age > A->age);
   if (swap) {
     code |= ORC_SWAP;
     *A = *C;
     orc_reset(C, x, p);
+    if (quant) orc_quantize(C);
   }
 
   {
@@ -533,6 +563,42 @@ int orc_forward_grid(int64_t T, int64_t H, int64_t W, int32_t b, const double* f
     }
     mean_a[k] = A.mean; var_a[k] = A.var; age_a[k] = A.age;
     mean_c[k] = C.mean; var_c[k] = C.var; age_c[k] = C.age;
+  }
+  return 0;
+}
+
+/*
+ * The 8-bit as-run model of the appendix: 8-bit frames, means and variances
+ * stored in 8-bit images (orc_u8 on every write), FP64 arithmetic in between.
+ * Same decisions and order as orc_forward; frames, means and variances are
+ * uint8 arrays here.
+ */
+int orc_forward_u8(int64_t T, int64_t N, const uint8_t* frames, uint8_t* mean_a, uint8_t* var_a,
+                   int32_t* age_a, uint8_t* mean_c, uint8_t* var_c, int32_t* age_c,
+                   const orc_params* p, uint8_t* masks, uint8_t* codes, int nthreads) {
+  int64_t nchunk, c;
+  if (orc_check(p) || T < 0 || N < 0) return -1;
+  if (T > 0 && N > 0 && (!frames || !mean_a || !var_a || !age_a || !mean_c || !var_c || !age_c))
+    return -1;
+  orc_set_threads(nthreads);
+  nchunk = (N + ORC_CHUNK - 1) / ORC_CHUNK;
+#pragma omp parallel for schedule(static)
+  for (c = 0; c < nchunk; ++c) {
+    int64_t p0 = c * ORC_CHUNK, p1 = p0 + ORC_CHUNK < N ? p0 + ORC_CHUNK : N;
+    int64_t t, i;
+    for (t = 0; t < T; ++t) {
+      for (i = p0; i < p1; ++i) {
+        int64_t e = t * N + i;
+        orc_model A = {(double)mean_a[i], (double)var_a[i], age_a[i]};
+        orc_model C = {(double)mean_c[i], (double)var_c[i], age_c[i]};
+        orc_tape tp;
+        uint8_t code = orc_step_q(&A, &C, (double)frames[e], p, -1, &tp, NULL, 1);
+        mean_a[i] = (uint8_t)A.mean; var_a[i] = (uint8_t)A.var; age_a[i] = A.age;
+        mean_c[i] = (uint8_t)C.mean; var_c[i] = (uint8_t)C.var; age_c[i] = C.age;
+        if (masks) masks[e] = (code & ORC_FG) ? 255 : 0;
+        if (codes) codes[e] = code;
+      }
+    }
   }
   return 0;
 }
