@@ -2,7 +2,8 @@
 """Throughput of the DSGM hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--legs main,mixed,video,filtered,warped,grid,attainable,adjoint,batched,largest]
+                    [--legs main,mixed,video,filtered,warped,grid,streaming,attainable,adjoint,
+                            batched,largest]
                     [--no-cpu-baseline]
 
 Main workload (the `value`): the plain method in FP64, one instance of
@@ -25,6 +26,8 @@ Secondary legs, reported under "legs" (same timing method):
   warped   motion-compensated update: 100 frames, one launch per frame, each with
            its own camera homography (the model is gathered through it), FP64
   grid     Yi et al.'s grid model (4x4-pixel blocks) on the main workload's frames
+  streaming  one call per frame (T = 1): FP64 against the appendix's 8-bit as-run
+           model, whose state is 6 bytes per pixel instead of 68
   attainable  the same bytes as the forward and backward kernels moved by kernels
            with no model arithmetic: the attainable HBM rate of each access pattern
   adjoint  FP32 frames and state, bg on, checkpoints every 32 frames, upstream
@@ -307,6 +310,44 @@ def leg_grid(args, dsgm, sdev, torch):
     return out
 
 
+def leg_streaming(args, dsgm, sdev, torch):
+    """Streaming, one call per frame (T = 1), 1920x2560 x 50 frames: the model
+    state goes through HBM every frame.  FP64 (68 bytes of state per pixel,
+    read and written) against the appendix's 8-bit as-run model (6 bytes), on
+    the structured video at 8-bit levels, seed 1."""
+    import numpy as np
+    T, H, W, seed = 50, 1920, 2560, 1
+    stream = torch.cuda.current_stream()
+    steps = max(2, args.steps // 4)
+    elems, px = T * H * W, H * W
+    out = {"workload": "1920x2560 x 50 frames, one dsgm_forward call per frame"}
+    v = sdev.video(seed, T, H, W, torch.float64)                       # q/128, q in -128..127
+    for name, frames, st_dtype, p, st_bytes, in_b in (
+            ("fp64", v, torch.float64, dsgm.dsgm_params_default(2.0), 34, 8),
+            ("u8_as_run", (v * 128 + 128).to(torch.uint8), torch.uint8,
+             dsgm.dsgm_params_default(255.0, dsgm.MASK_PRINTED), 6, 1)):
+        if name == "u8_as_run":
+            p.weight_rule = dsgm.WEIGHT_APPENDIX
+        st = dsgm.State.empty(H, W, st_dtype)
+        dsgm.dsgm_state_init_from_frame(frames[0], st, p)
+        masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+
+        def run():
+            for t in range(T):
+                dsgm.dsgm_forward(frames[t:t + 1], st, p, masks[t:t + 1])
+
+        ms, kk = timed(run, steps, 1, stream)
+        out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                     "roofline": roof(elems * (in_b + 1 + 2 * st_bytes), float(sum(kk) / len(kk))),
+                     "bytes_per_element": in_b + 1 + 2 * st_bytes}
+        del st, masks, frames
+    del v
+    torch.cuda.empty_cache()
+    out["speedup_u8_over_fp64"] = round(out["u8_as_run"]["elements_per_s"] /
+                                        out["fp64"]["elements_per_s"], 3)
+    return out
+
+
 def leg_attainable(args, dsgm, sdev, torch):
     """Attainable HBM rate of each kernel's access pattern: kernels that move the
     same bytes in the same order, widths and cache hints as the forward and
@@ -562,7 +603,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--legs",
-                    default="main,mixed,video,filtered,warped,grid,attainable,adjoint,batched,largest")
+                    default="main,mixed,video,filtered,warped,grid,streaming,attainable,adjoint,"
+                            "batched,largest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter scale)")
@@ -619,7 +661,7 @@ def main():
     out_legs = {}
     progress(f"main leg done: {value / 1e9:.1f} G elements/s")
     for name, fn in (("mixed", leg_mixed), ("video", leg_video), ("filtered", leg_filtered),
-                     ("warped", leg_warped), ("grid", leg_grid),
+                     ("warped", leg_warped), ("grid", leg_grid), ("streaming", leg_streaming),
                      ("attainable", leg_attainable), ("adjoint", leg_adjoint),
                      ("batched", leg_batched), ("largest", leg_largest)):
         if name in legs:

@@ -57,8 +57,8 @@ typedef enum {
   DSGM_E_UNSUPPORTED = -7  /* valid but not implemented                       */
 } dsgm_status;
 
-/* storage type of the frames */
-typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2 } dsgm_in_dtype;
+/* storage type of the frames (U8: 8-bit frames, 0..255, for the as-run model) */
+typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2, DSGM_IN_U8 = 3 } dsgm_in_dtype;
 
 /* type of the model state and of every arithmetic operation, and of the bulk
  * output arrays (bg and every gradient array):
@@ -67,8 +67,14 @@ typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2 } dsgm_in_dtyp
  *   F64_IO32  state and arithmetic in FP64, bg and gradient arrays in FP32
  *             (F32/BF16 frames): decisions and state are those of the FP64
  *             path, the arrays are its values rounded once to FP32, at the
- *             memory cost of FP32 (the state is per pixel, not per frame) */
-typedef enum { DSGM_ACC_F64 = 0, DSGM_ACC_F32 = 1, DSGM_ACC_F64_IO32 = 2 } dsgm_acc;
+ *             memory cost of FP32 (the state is per pixel, not per frame)
+ *   U8        the appendix's as-run model (U8 frames only): means and
+ *             variances kept as uint8 planes, FP64 arithmetic, every stored
+ *             value converted to an integer with its fraction dropped and
+ *             limited to [0, 255] (var_init too); the tests, the swap and the
+ *             mask see the stored values.  dsgm_forward (masks, codes) and
+ *             dsgm_state_init_from_frame only; other calls return DSGM_E_DTYPE */
+typedef enum { DSGM_ACC_F64 = 0, DSGM_ACC_F32 = 1, DSGM_ACC_F64_IO32 = 2, DSGM_ACC_U8 = 3 } dsgm_acc;
 
 /* learning weight of a model of age a: Sec. 2.2 gives 1/(a+1); the appendix
  * computes 1/a.  The complementary weight is 1 - w in the accumulation type. */

@@ -33,9 +33,11 @@ int hip_fail(hipError_t e, const char* where) {
   return fail(DSGM_E_HIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-size_t in_size(int d) { return d == DSGM_IN_F64 ? 8 : d == DSGM_IN_F32 ? 4 : 2; }
+size_t in_size(int d) {
+  return d == DSGM_IN_F64 ? 8 : d == DSGM_IN_F32 ? 4 : d == DSGM_IN_BF16 ? 2 : 1;
+}
 // element size of the model state (and of every arithmetic operation)
-size_t acc_size(int a) { return a == DSGM_ACC_F32 ? 4 : 8; }
+size_t acc_size(int a) { return a == DSGM_ACC_F32 ? 4 : a == DSGM_ACC_U8 ? 1 : 8; }
 // element size of bg and of every gradient array
 size_t io_size(int a) { return a == DSGM_ACC_F64 ? 8 : 4; }
 
@@ -71,6 +73,18 @@ int check_types(int in_dtype, int acc) {
     return fail(DSGM_E_DTYPE, "F64 frames need ACC_F64");
   return DSGM_OK;
 }
+
+// as check_types, and also the 8-bit as-run pair (U8 frames with U8 state),
+// which only dsgm_forward and dsgm_state_init_from_frame implement
+int check_types_u8(int in_dtype, int acc) {
+  if (in_dtype == DSGM_IN_U8 && acc == DSGM_ACC_U8) return DSGM_OK;
+  if (in_dtype == DSGM_IN_U8 || acc == DSGM_ACC_U8)
+    return fail(DSGM_E_DTYPE, "U8 frames and U8 state go together");
+  return check_types(in_dtype, acc);
+}
+
+// the 8-bit storage rule applied to a parameter (var_init of a reset model)
+double stored_u8(double v) { return v > 0.0 ? (v >= 255.0 ? 255.0 : std::trunc(v)) : 0.0; }
 
 // frames-like arrays: per-frame extent must fit 31 bits of elements and bytes
 int check_shape(const dsgm_shape& s, size_t max_elem_bytes) {
@@ -231,7 +245,7 @@ int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_
                                dsgm_acc acc, const dsgm_params* params, dsgm_state* state,
                                hipStream_t stream) {
   int rc;
-  if ((rc = check_types(in_dtype, acc))) return rc;
+  if ((rc = check_types_u8(in_dtype, acc))) return rc;
   if ((rc = check_params(params))) return rc;
   dsgm_shape one = shape;
   one.T = 1;
@@ -262,7 +276,8 @@ int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_
   a.W = shape.W;
   a.row_stride = shape.row_stride;
   a.var_init = params->var_init;
-  hipError_t e = dsgm::launch_init(a, in_dtype, acc, stream);
+  hipError_t e = acc == DSGM_ACC_U8 ? dsgm::launch_init_u8(a, stream)
+                                    : dsgm::launch_init(a, in_dtype, acc, stream);
   if (e != hipSuccess) return hip_fail(e, "dsgm_state_init_from_frame launch");
   return ok();
 }
@@ -272,8 +287,11 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
                  void* ckpt, size_t ckpt_bytes, int32_t ckpt_every, uint8_t* codes,
                  hipStream_t stream) {
   int rc;
-  if ((rc = check_types(in_dtype, acc))) return rc;
+  if ((rc = check_types_u8(in_dtype, acc))) return rc;
   if ((rc = check_params(params))) return rc;
+  const bool as_run = acc == DSGM_ACC_U8;
+  if (as_run && (bg || ckpt))
+    return fail(DSGM_E_UNSUPPORTED, "the 8-bit as-run model has no bg or checkpoint output");
   const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
   if ((rc = check_shape(shape, ie > oe ? ie : oe))) return rc;
   if (!state) return fail(DSGM_E_ARG, "state is NULL");
@@ -299,8 +317,9 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   const int widest = pick_vector(shape, ptrs, elem, 10);
   int P = std::min(widest, preferred_vector(in_dtype, acc));
   if (ckpt && !aligned(ckpt, ae * P)) P = 1;
+  if (as_run) P = widest;  // four one-byte pixels per lane when the layout allows
   if (g_vector_override && widest % g_vector_override == 0) P = g_vector_override;
-  if (codes) P = 1;  // the decision-code (debug) variants run one pixel per lane
+  if (codes && !as_run) P = 1;  // the decision-code (debug) variants run one pixel per lane
 
   dsgm::FwdArgs a;
   memset(&a, 0, sizeof(a));
@@ -328,7 +347,7 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   a.ngroups = shape.H * (shape.W / P);
   a.theta_s = params->theta_s;
   a.theta_d = params->theta_d;
-  a.var_init = params->var_init;
+  a.var_init = as_run ? stored_u8(params->var_init) : params->var_init;
   a.var_floor = params->var_floor;
   a.mask_floor = params->mask_floor;
   a.age_max = params->age_max;
@@ -338,7 +357,8 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   const int flags = (bg ? dsgm::FWD_BG : 0) | (codes ? dsgm::FWD_CODES : 0) |
                     (ckpt ? dsgm::FWD_CKPT : 0) |
                     (params->mask_rule == DSGM_MASK_PRINTED ? dsgm::FWD_PRINTED : 0);
-  hipError_t e = dsgm::launch_forward(a, in_dtype, acc, P, flags, block, stream);
+  hipError_t e = as_run ? dsgm::launch_fwd_u8(a, P, flags, block, stream)
+                        : dsgm::launch_forward(a, in_dtype, acc, P, flags, block, stream);
   if (e != hipSuccess) return hip_fail(e, "dsgm_forward launch");
   return ok();
 }

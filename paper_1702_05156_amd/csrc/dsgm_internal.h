@@ -91,6 +91,11 @@ struct BatchArgs {
   int32_t age_max, weight_rule, mask_rule;
 };
 
+// The 8-bit as-run model (dsgm_u8.hip): U8 frames and U8 state planes, FwdArgs
+// with var_init already in stored form; flags FWD_CODES and FWD_PRINTED only.
+hipError_t launch_fwd_u8(const FwdArgs& a, int P, int flags, int block, hipStream_t stream);
+hipError_t launch_init_u8(const FwdArgs& a, hipStream_t stream);
+
 // Arguments of the forward with fused preprocessing (dsgm_pre.hip).
 struct PreArgs {
   const void* frames;

@@ -1,0 +1,170 @@
+// dsgm_u8.hip -- the 8-bit as-run model of the appendix (internal).
+//
+// The appendix's inner update reads 8-bit frames and keeps each model's mean
+// and variance in 8-bit images: the arithmetic is double precision, and every
+// value written back is converted to an integer, the fraction dropped (here
+// also limited to [0, 255], where the conversion has no defined result).  The
+// tests, the swap and the mask then see the stored values.  This kernel runs
+// that model time-fused like fwd_kernel: one lane owns P adjacent pixels of a
+// row for all T frames with their models in registers (as doubles holding the
+// stored integers), and per frame reads P frame bytes and writes P mask bytes.
+// The state is 6 bytes per pixel instead of 68, which is what a T = 1
+// streaming caller moves per frame.
+#include "dsgm_fwd_impl.h"
+
+namespace dsgm {
+
+namespace u8 {
+
+using fwd::fill_table;
+using fwd::ld_stream;
+using fwd::make_consts;
+using fwd::st_stream;
+
+// the storage rule of an 8-bit image: drop the fraction, limit to [0, 255]
+__device__ __forceinline__ double stored(double v) {
+  return __builtin_fmin(255.0, __builtin_fmax(0.0, __builtin_trunc(v)));
+}
+
+template <int P, bool CODES, bool PRINTED>
+__global__ void __launch_bounds__(256) u8_kernel(const FwdArgs a) {
+  __shared__ TableEntry<double> tbl[TABLE_SIZE];
+  fill_table<double>(tbl, a.weight_rule, a.age_max, a.var_init);  // var_init already stored
+  const StepConsts<double> k =
+      make_consts<double>(a.theta_s, a.theta_d, a.var_init, a.var_floor, a.mask_floor);
+
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= a.ngroups) return;  // no barrier follows
+  const int64_t h = g / a.groups_per_row;
+  const int64_t w = (g - h * a.groups_per_row) * P;
+  const int64_t pix = h * a.W + w;
+  const int64_t foff = h * a.row_stride + w;
+
+  Model<double> s[P];
+  {
+    const Vec<uint8_t, P> mA = *reinterpret_cast<const Vec<uint8_t, P>*>(
+        static_cast<const uint8_t*>(a.mean_a) + pix);
+    const Vec<uint8_t, P> vA = *reinterpret_cast<const Vec<uint8_t, P>*>(
+        static_cast<const uint8_t*>(a.var_a) + pix);
+    const Vec<uint8_t, P> mC = *reinterpret_cast<const Vec<uint8_t, P>*>(
+        static_cast<const uint8_t*>(a.mean_c) + pix);
+    const Vec<uint8_t, P> vC = *reinterpret_cast<const Vec<uint8_t, P>*>(
+        static_cast<const uint8_t*>(a.var_c) + pix);
+    const Vec<uint8_t, P> aA = *reinterpret_cast<const Vec<uint8_t, P>*>(a.age_a + pix);
+    const Vec<uint8_t, P> aC = *reinterpret_cast<const Vec<uint8_t, P>*>(a.age_c + pix);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      s[q].mA = double(mA.v[q]);
+      s[q].vA = double(vA.v[q]);
+      s[q].mC = double(mC.v[q]);
+      s[q].vC = double(vC.v[q]);
+      s[q].aA = aA.v[q];
+      s[q].aC = aC.v[q];
+    }
+  }
+
+  const uint8_t* frames = static_cast<const uint8_t*>(a.frames);
+  constexpr int U = 8;  // frames in flight
+  auto frame_at = [&](int64_t t) { return ld_stream<uint8_t, P>(frames + t * a.frame_stride + foff); };
+  auto do_frame = [&](const Vec<uint8_t, P>& xv, int64_t t) {
+    double xs[P];
+    StepRecord<double> r[P];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      xs[q] = double(xv.v[q]);
+      r[q] = step_core<double>(s[q], xs[q], k, tbl);
+      // the matched model (or the reset candidate) is written to 8-bit storage;
+      // the other models hold stored values already, which the rule keeps
+      s[q].mA = stored(s[q].mA);
+      s[q].vA = stored(s[q].vA);
+      s[q].mC = stored(s[q].mC);
+      s[q].vC = stored(s[q].vC);
+      any |= r[q].swap;
+    }
+    if (any_lane(any)) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) apply_swap<double>(s[q], xs[q], k, r[q].swap);
+    }
+    Vec<uint8_t, P> mk, cd;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      r[q].fg = fg_of<double, PRINTED>(s[q], xs[q], k);
+      mk.v[q] = r[q].fg ? uint8_t(255) : uint8_t(0);
+      cd.v[q] = uint8_t(code_of<double>(r[q]));
+    }
+    const int64_t o = t * a.frame_stride + foff;
+    st_stream<uint8_t, P>(a.masks + o, mk);
+    if (CODES) *reinterpret_cast<Vec<uint8_t, P>*>(a.codes + o) = cd;
+  };
+  const int64_t T = a.T;
+  int64_t t = 0;
+  for (; t + U <= T; t += U) {
+    Vec<uint8_t, P> xb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xb[u] = frame_at(t + u);
+#pragma unroll
+    for (int u = 0; u < U; ++u) do_frame(xb[u], t + u);
+  }
+  for (; t < T; ++t) do_frame(frame_at(t), t);
+
+  Vec<uint8_t, P> mA, vA, mC, vC, aA, aC;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    mA.v[q] = uint8_t(s[q].mA);
+    vA.v[q] = uint8_t(s[q].vA);
+    mC.v[q] = uint8_t(s[q].mC);
+    vC.v[q] = uint8_t(s[q].vC);
+    aA.v[q] = uint8_t(s[q].aA);
+    aC.v[q] = uint8_t(s[q].aC);
+  }
+  *reinterpret_cast<Vec<uint8_t, P>*>(static_cast<uint8_t*>(a.mean_a) + pix) = mA;
+  *reinterpret_cast<Vec<uint8_t, P>*>(static_cast<uint8_t*>(a.var_a) + pix) = vA;
+  *reinterpret_cast<Vec<uint8_t, P>*>(static_cast<uint8_t*>(a.mean_c) + pix) = mC;
+  *reinterpret_cast<Vec<uint8_t, P>*>(static_cast<uint8_t*>(a.var_c) + pix) = vC;
+  *reinterpret_cast<Vec<uint8_t, P>*>(a.age_a + pix) = aA;
+  *reinterpret_cast<Vec<uint8_t, P>*>(a.age_c + pix) = aC;
+}
+
+template <int P>
+hipError_t launch_p(const FwdArgs& a, int flags, int block, hipStream_t stream) {
+  const dim3 grid{uint32_t((a.ngroups + block - 1) / block), 1, 1}, blk{uint32_t(block), 1, 1};
+  const bool codes = (flags & FWD_CODES) != 0, printed = (flags & FWD_PRINTED) != 0;
+  if (codes && printed) hipLaunchKernelGGL((u8_kernel<P, true, true>), grid, blk, 0, stream, a);
+  else if (codes) hipLaunchKernelGGL((u8_kernel<P, true, false>), grid, blk, 0, stream, a);
+  else if (printed) hipLaunchKernelGGL((u8_kernel<P, false, true>), grid, blk, 0, stream, a);
+  else hipLaunchKernelGGL((u8_kernel<P, false, false>), grid, blk, 0, stream, a);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) u8_init_kernel(const FwdArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.H * a.W) return;
+  const int64_t h = i / a.W, w = i - h * a.W;
+  const uint8_t x = static_cast<const uint8_t*>(a.frames)[h * a.row_stride + w];
+  const uint8_t v = uint8_t(stored(a.var_init));
+  static_cast<uint8_t*>(a.mean_a)[i] = x;
+  static_cast<uint8_t*>(a.mean_c)[i] = x;
+  static_cast<uint8_t*>(a.var_a)[i] = v;
+  static_cast<uint8_t*>(a.var_c)[i] = v;
+  a.age_a[i] = 1;
+  a.age_c[i] = 1;
+}
+
+}  // namespace u8
+
+hipError_t launch_fwd_u8(const FwdArgs& a, int P, int flags, int block, hipStream_t stream) {
+  if (flags & (FWD_BG | FWD_CKPT)) return hipErrorInvalidValue;
+  if (P == 4) return u8::launch_p<4>(a, flags, block, stream);
+  if (P == 2) return u8::launch_p<2>(a, flags, block, stream);
+  if (P == 1) return u8::launch_p<1>(a, flags, block, stream);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_init_u8(const FwdArgs& a, hipStream_t stream) {
+  const int64_t n = a.H * a.W;
+  hipLaunchKernelGGL(u8::u8_init_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace dsgm

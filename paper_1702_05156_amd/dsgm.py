@@ -22,17 +22,20 @@ LIB_PATH = os.path.join(_HERE, "libdsgm.so")
 DSGM_OK = 0
 STATUS = {0: "DSGM_OK", -1: "DSGM_E_ARG", -2: "DSGM_E_SHAPE", -3: "DSGM_E_DTYPE",
           -4: "DSGM_E_ALIGN", -5: "DSGM_E_WORKSPACE", -6: "DSGM_E_HIP", -7: "DSGM_E_UNSUPPORTED"}
-IN_F64, IN_F32, IN_BF16 = 0, 1, 2
-ACC_F64, ACC_F32, ACC_F64_IO32 = 0, 1, 2
+IN_F64, IN_F32, IN_BF16, IN_U8 = 0, 1, 2, 3
+ACC_F64, ACC_F32, ACC_F64_IO32, ACC_U8 = 0, 1, 2, 3
 WEIGHT_EQ, WEIGHT_APPENDIX = 0, 1
 MASK_VARIANCE, MASK_PRINTED = 0, 1
 CODE_HIT_A, CODE_HIT_C, CODE_RESET, CODE_SWAP, CODE_FG = 1, 2, 4, 8, 16
 
-_IN_DTYPES = {torch.float64: IN_F64, torch.float32: IN_F32, torch.bfloat16: IN_BF16}
-_ACC_DTYPES = {torch.float64: ACC_F64, torch.float32: ACC_F32}
+_IN_DTYPES = {torch.float64: IN_F64, torch.float32: IN_F32, torch.bfloat16: IN_BF16,
+              torch.uint8: IN_U8}
+_ACC_DTYPES = {torch.float64: ACC_F64, torch.float32: ACC_F32, torch.uint8: ACC_U8}
 # dtype of bg and of the gradient arrays, and of the model state, per dsgm_acc
-ACC_TORCH = {ACC_F64: torch.float64, ACC_F32: torch.float32, ACC_F64_IO32: torch.float32}
-STATE_TORCH = {ACC_F64: torch.float64, ACC_F32: torch.float32, ACC_F64_IO32: torch.float64}
+ACC_TORCH = {ACC_F64: torch.float64, ACC_F32: torch.float32, ACC_F64_IO32: torch.float32,
+             ACC_U8: torch.uint8}
+STATE_TORCH = {ACC_F64: torch.float64, ACC_F32: torch.float32, ACC_F64_IO32: torch.float64,
+               ACC_U8: torch.uint8}
 
 
 class DSGMError(RuntimeError):
