@@ -78,16 +78,19 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
   // guard).
   auto chunk = [&](Model<Acc> s, const int64_t c0, const int len, auto full_tag) {
     constexpr bool FULL = decltype(full_tag)::value;
-    Acc xs[KC], gb[KC];
+    // frames and upstream gradients are held in their storage types (half the
+    // registers of FP64 when the arrays are FP32) and widened at use
+    In xs[KC];
+    Io gb[KC];
 #pragma unroll
     for (int i = 0; i < KC; ++i)
-      if (FULL || i < len) xs[i] = x_at(c0 + i);
+      if (FULL || i < len) xs[i] = *reinterpret_cast<const In*>(frames + (c0 + i) * fs_in + off_in);
     Acc tape_d[KC];
     uint32_t tape_m[(KC + 1) / 2];
 #pragma unroll
     for (int i = 0; i < KC; ++i) {
       if (FULL || i < len) {
-        const StepRecord<Acc> r = step_rec<Acc, false>(s, xs[i], k, tbl);  // mask unused
+        const StepRecord<Acc> r = step_rec<Acc, false>(s, to_acc<In, Acc>(xs[i]), k, tbl);
         tape_d[i] = r.d;
         const uint32_t m = uint32_t(r.idx) | (r.hitA ? 0x200u : 0u) | (r.swap ? 0x400u : 0u);
         if (i % 2 == 0)
@@ -99,15 +102,15 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
     // the gradient loads reuse the frames' registers (dead after the replay)
 #pragma unroll
     for (int i = 0; i < KC; ++i) {
-      gb[i] = Acc(0);
+      gb[i] = Io(0);
       if (HAS_GBG && (FULL || i < len))
-        gb[i] = Acc(*reinterpret_cast<const Io*>(gbg + (c0 + i) * fs_io + off_io));
+        gb[i] = *reinterpret_cast<const Io*>(gbg + (c0 + i) * fs_io + off_io);
     }
 #pragma unroll
     for (int i = KC - 1; i >= 0; --i) {
       if (FULL || i < len) {
         const uint32_t m = (tape_m[i / 2] >> (16 * (i % 2))) & 0xFFFFu;
-        const Acc gx = reverse_step<Acc, HAS_GBG>(adj, gb[i], tape_d[i], int(m & 0x1FFu),
+        const Acc gx = reverse_step<Acc, HAS_GBG>(adj, Acc(gb[i]), tape_d[i], int(m & 0x1FFu),
                                                   (m & 0x200u) != 0, (m & 0x400u) != 0, tbl);
         *reinterpret_cast<Io*>(gfr + (c0 + i) * fs_io + off_io) = Io(gx);  // rounded once
       }
@@ -256,8 +259,8 @@ hipError_t launch_backward(const BwdArgs& a, int in_dtype, int acc, hipStream_t 
     if (in_dtype == 1) return launch_bwd_k<float, float, float, 32>(a, stream);
     if (in_dtype == 2) return launch_bwd_k<bf16_t, float, float, 32>(a, stream);
   } else if (acc == 2) {
-    if (in_dtype == 1) return launch_bwd_k<float, double, float, 16>(a, stream);
-    if (in_dtype == 2) return launch_bwd_k<bf16_t, double, float, 16>(a, stream);
+    if (in_dtype == 1) return launch_bwd_k<float, double, float, 32>(a, stream);
+    if (in_dtype == 2) return launch_bwd_k<bf16_t, double, float, 32>(a, stream);
   }
   return hipErrorInvalidValue;
 }
