@@ -525,7 +525,10 @@ def leg_batched(args, dsgm, sdev, torch):
            enumerate(shapes)]
     items = _batch_items(shapes, range(len(shapes)), dsgm, sdev, torch, torch.bfloat16,
                          torch.float32, st0)
-    batch = dsgm.Batch(items)
+    # the tile width (pixels per lane) of the plan is picked by the autotuner
+    from paper_1702_05156_amd import tune
+    tuned = tune.tune_batched(items, p, store=False)
+    batch = dsgm.Batch(items, vector=tuned["vector"])
     batch.run(p)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -584,6 +587,8 @@ def leg_batched(args, dsgm, sdev, torch):
                        "masks only, seed 3",
            "instances": len(shapes), "total_elements": int(elems), "work_items": n_items,
            "persistent_workgroups": grid,
+           "autotuned_pixels_per_lane": tuned["vector"],
+           "autotune_candidates_ms": {str(c["vector"]): round(c["ms"], 3) for c in tuned["candidates"]},
            "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
            "roofline": roof(alg, float(sum(kk) / len(kk))),
            "fp64_form": {"workload": "the same 512 instances, fp64 frames (same values) and fp64 "

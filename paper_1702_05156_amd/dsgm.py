@@ -545,7 +545,9 @@ class Batch:
     current stream (capturable into a CUDA/HIP graph).
     """
 
-    def __init__(self, items, in_dtype=None, acc=None):
+    def __init__(self, items, in_dtype=None, acc=None, vector: int = 0):
+        """``vector`` (pixels per lane, 1/2/4; 0 = the library's default) is the
+        tile width of the plan; ``tune.tune_batched`` picks it by measurement."""
         self.items = list(items)
         if not self.items:
             raise ValueError("empty batch")
@@ -557,15 +559,21 @@ class Batch:
                 raise ValueError("all instances of a batch share the frame and state dtypes")
         arr = (Instance * len(self.items))(*(_instance(*it, acc=self.acc) for it in self.items))
         self._arr = arr
-        nbytes = int(lib.dsgm_batch_plan_bytes(arr, len(self.items), self.in_dtype, self.acc))
-        if nbytes == 0:
-            raise DSGMError("dsgm_batch_plan_bytes", -1, lib.dsgm_last_error().decode())
-        self.plan_buffer = torch.empty(nbytes, dtype=torch.uint8, device=fr0.device)
-        self.plan = BatchPlan()
-        _check("dsgm_plan_batched",
-               lib.dsgm_plan_batched(arr, len(self.items), self.in_dtype, self.acc,
-                                     _ptr(self.plan_buffer), nbytes, ctypes.byref(self.plan),
-                                     _stream()))
+        if vector:
+            dsgm_set_launch(0, vector)  # the width the plan's size and items are made for
+        try:
+            nbytes = int(lib.dsgm_batch_plan_bytes(arr, len(self.items), self.in_dtype, self.acc))
+            if nbytes == 0:
+                raise DSGMError("dsgm_batch_plan_bytes", -1, lib.dsgm_last_error().decode())
+            self.plan_buffer = torch.empty(nbytes, dtype=torch.uint8, device=fr0.device)
+            self.plan = BatchPlan()
+            _check("dsgm_plan_batched",
+                   lib.dsgm_plan_batched(arr, len(self.items), self.in_dtype, self.acc,
+                                         _ptr(self.plan_buffer), nbytes, ctypes.byref(self.plan),
+                                         _stream()))
+        finally:
+            if vector:
+                dsgm_set_launch(0, 0)
 
     def run(self, params: Params) -> None:
         _check("dsgm_forward_batched",

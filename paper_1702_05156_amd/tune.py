@@ -13,6 +13,11 @@ file keyed by the problem's types, output set and sizes:
 
 ``tuned(key)`` is a context manager that applies a cached shape through
 ``dsgm_set_launch`` for the calls inside it (the setting is per process).
+
+``tune_batched`` does the same for a batch of uneven instances: it plans the
+batch with each tile width (pixels per lane: 1, 2, 4), times one persistent
+launch of each, and returns (and caches) the fastest; ``Batch(items,
+vector=best["vector"])`` then plans with it.
 """
 from __future__ import annotations
 
@@ -126,5 +131,52 @@ def tune_forward(frames: torch.Tensor, state: "dsgm.State", params: "dsgm.Params
             cache = _load()
             cache[key] = {"block": best["block"], "vector": best["vector"],
                           "ms_per_frame": best["ms_per_frame"]}
+            _store(cache)
+    return out
+
+
+def batched_key(items) -> str:
+    fr0, st0 = items[0][0], items[0][1]
+    total = sum(int(fr.numel()) for fr, *_ in items)
+    return (f"batched/{str(fr0.dtype)[6:]}/{str(st0.mean_a.dtype)[6:]}/n{len(items)}/"
+            f"e{total}")
+
+
+def tune_batched(items, params: "dsgm.Params", *, reps: int = 2, store: bool = True) -> dict:
+    """Time one persistent batched launch per tile width on these instances.
+
+    The instances' states advance with every launch (the timing does not
+    depend on the values).  Returns and caches {"vector", "ms", "candidates"}.
+    """
+    results = []
+    stream = torch.cuda.current_stream()
+    with _lock:
+        for vec in VECTORS:
+            try:
+                b = dsgm.Batch(items, vector=vec)
+            except dsgm.DSGMError:
+                continue
+            if b.plan.vector != vec:
+                continue  # a layout the instances do not allow
+            b.run(params)  # warm
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                b.run(params)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            results.append({"vector": vec, "ms": e0.elapsed_time(e1) / reps,
+                            "work_items": int(b.plan.n_items)})
+            del b
+    if not results:
+        raise RuntimeError("no tile width is allowed by these instances")
+    best = min(results, key=lambda r: r["ms"])
+    out = dict(best, candidates=results)
+    if store:
+        key = batched_key(items)
+        with _lock:
+            cache = _load()
+            cache[key] = {"vector": best["vector"], "ms": best["ms"]}
             _store(cache)
     return out
