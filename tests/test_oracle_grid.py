@@ -77,3 +77,17 @@ def test_block_variance_term_dominates_the_mean_distance():
     mean = (1 - w) * 0.2 + w * 0.25
     want = (1 - w) * 1.0 + w * max((mean - v) ** 2 for v in (0.0, 0.5, 0.25, 0.25))
     assert g["var_a"][0] == pytest.approx(want, rel=1e-15)
+
+
+def test_masks_are_per_pixel_against_the_block_model():
+    """A block of equal pixels with one outlier: the block model matches and
+    stays near the common value, so only the outlier is foreground."""
+    T, H, W, b = 1, 4, 4, 4
+    x = np.full((T, H, W), 0.25)
+    x[0, 2, 1] = 0.9
+    st = {"mean_a": np.array([0.25]), "var_a": np.array([0.01]), "mean_c": np.array([-1.0]),
+          "var_c": np.array([0.01]), "age_a": np.array([30]), "age_c": np.array([1])}
+    g = oracle.forward_grid(x, st, P, b)
+    assert g["codes"][0, 0] & 1                  # the block matched A
+    fg = g["masks"][0] != 0
+    assert fg[2, 1] and fg.sum() == 1

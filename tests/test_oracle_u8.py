@@ -23,12 +23,18 @@ def _setup(seed, T, N):
     return x, st
 
 
-@pytest.mark.parametrize("rule,mrule", [(1, 1), (0, 0), (1, 0)])
-def test_each_frame_is_the_real_step_then_the_storage_rule(rule, mrule):
+@pytest.mark.parametrize("rule,mrule,var_init", [(1, 1, None), (0, 0, None), (1, 0, None),
+                                                  (1, 1, 100.5), (0, 1, 101.9)])
+def test_each_frame_is_the_real_step_then_the_storage_rule(rule, mrule, var_init):
+    """Per-frame calls (state stored between frames) equal one call over all
+    frames; a fractional var_init exercises the storage of reset and swapped
+    candidates within a call."""
     T, N = 60, 500
     x, st = _setup(1, T, N)
     p = oracle.default_params(255.0, mask_rule=mrule)
     p.weight_rule = rule
+    if var_init is not None:
+        p.var_init = var_init
     full = oracle.forward_u8(x, st, p)
     cur = {k: np.asarray(v) for k, v in st.items()}
     for t in range(T):
@@ -73,3 +79,25 @@ def test_storage_rule_saturates_and_truncates():
     p.var_init = 17.9
     out = oracle.forward_u8(np.array([[10]], np.uint8), dict(st, var_a=[0], mean_c=[200]), p)
     assert out["var_c"][0] == 17
+
+
+def test_swapped_in_candidate_is_stored_before_it_is_used():
+    """Frame 0 swaps (C older than A) and resets C to (x, var_init); frame 1 fails
+    A and matches C, whose stored variance is trunc(var_init): 101.9 -> 101.
+    One call over both frames equals two one-frame calls (state stored between
+    them), and the hand result: mean (100 + 111) / 2 = 105.5 -> 105, variance
+    101 / 2 + (105.5 - 111)^2 / 2 = 65.625 -> 65."""
+    p = oracle.default_params(255.0, mask_rule=1)
+    p.weight_rule = 0
+    p.var_init = 101.9
+    st = {"mean_a": [10], "var_a": [1], "mean_c": [100], "var_c": [1], "age_a": [1],
+          "age_c": [5]}
+    x = np.array([[100], [111]], np.uint8)
+    both = oracle.forward_u8(x, st, p)
+    one = oracle.forward_u8(x[:1], st, p)
+    assert one["codes"][0, 0] & 8 and one["var_c"][0] == 101
+    two = oracle.forward_u8(x[1:], {k: one[k] for k in st}, p)
+    assert two["codes"][0, 0] & 2
+    assert two["mean_c"][0] == 105 and two["var_c"][0] == 65
+    for k in st:
+        assert np.array_equal(both[k], two[k]), k
