@@ -250,3 +250,37 @@ def test_grid_forward_validation():
                                         ctypes.byref(p), b, ctypes.byref(st), 1 << 20, None, None,
                                         None)
         assert rc == want, (b, rc)
+
+
+def test_empty_problems_of_the_extensions_need_no_gpu():
+    """T = 0, H = 0 or W = 0: every extension entry point returns OK at once."""
+    p = dsgm.dsgm_params_default(2.0)
+    st = dsgm._State(1 << 20, 1 << 21, 1 << 22, 1 << 23, 1 << 24, 1 << 25)
+    f = dsgm.gauss_filter(5, 1.0, True)
+    for sh in ((0, 8, 8, 8, 64), (4, 0, 8, 8, 64), (4, 8, 0, 0, 0)):
+        rc = lib.dsgm_forward_filtered(None, 0, dsgm.Shape(*sh), 0, ctypes.byref(p),
+                                       ctypes.byref(f), ctypes.byref(st), None, None, None, None,
+                                       None)
+        assert rc == 0, sh
+        rc = lib.dsgm_forward_grid(None, 0, dsgm.Shape(*sh), 0, ctypes.byref(p), 4,
+                                   ctypes.byref(st), None, None, None, None)
+        assert rc == 0, sh
+    m = (ctypes.c_double * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1)
+    st2 = dsgm._State(1 << 26, 1 << 27, 1 << 28, 1 << 29, 1 << 30, 1 << 31)
+    rc = lib.dsgm_forward_warped(None, 0, dsgm.Shape(1, 0, 8, 8, 0), 0, ctypes.byref(p), m,
+                                 ctypes.byref(st), ctypes.byref(st2), None, None, None, None)
+    assert rc == 0
+    p8 = dsgm.dsgm_params_default(255.0, 1)
+    rc = lib.dsgm_forward(None, 3, dsgm.Shape(0, 8, 8, 8, 64), 3, ctypes.byref(p8),
+                          ctypes.byref(st), None, None, None, 0, 0, None, None)
+    assert rc == 0
+    # the 8-bit model goes with 8-bit frames only, and has no bg or checkpoints
+    rc = lib.dsgm_forward(1 << 20, 1, dsgm.Shape(2, 8, 8, 8, 64), 3, ctypes.byref(p8),
+                          ctypes.byref(st), 1 << 20, None, None, 0, 0, None, None)
+    assert rc == -3
+    rc = lib.dsgm_forward(1 << 20, 3, dsgm.Shape(2, 8, 8, 8, 64), 3, ctypes.byref(p8),
+                          ctypes.byref(st), 1 << 20, 1 << 21, None, 0, 0, None, None)
+    assert rc == -7
+    rc = lib.dsgm_backward(1 << 20, 3, dsgm.Shape(2, 8, 8, 8, 64), 3, ctypes.byref(p8), None, 0,
+                           1, None, None, 1 << 20, None, None, None, 0, None)
+    assert rc == -3
