@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "dsgm.h"
+#include "dsgm_ext.h"
 #include "dsgm_internal.h"
 
 namespace {

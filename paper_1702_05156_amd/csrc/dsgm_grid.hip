@@ -14,6 +14,7 @@
 // lanes own neighbouring blocks, so every row access is contiguous across the
 // wavefront.  With FP64 state the block sum (row-major from 0), the division
 // by |G| and the update follow the order of a scalar evaluation.
+#include "dsgm_ext.h"
 #include "dsgm_fwd_impl.h"
 
 namespace dsgm {

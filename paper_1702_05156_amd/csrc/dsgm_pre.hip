@@ -29,6 +29,7 @@
 //
 // The blur sums run from 0 in index order with every product and sum rounded
 // (no contraction) for FP64 state, the order the oracle uses.
+#include "dsgm_ext.h"
 #include "dsgm_fwd_impl.h"
 
 namespace dsgm {

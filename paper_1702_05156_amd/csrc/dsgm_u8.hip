@@ -10,6 +10,7 @@
 // stored integers), and per frame reads P frame bytes and writes P mask bytes.
 // The state is 6 bytes per pixel instead of 68, which is what a T = 1
 // streaming caller moves per frame.
+#include "dsgm_ext.h"
 #include "dsgm_fwd_impl.h"
 
 namespace dsgm {

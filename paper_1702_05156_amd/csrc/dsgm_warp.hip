@@ -15,6 +15,7 @@
 //
 // With FP64 state the coordinates, weights and blends are evaluated with
 // every product and sum rounded in the order of a scalar evaluation.
+#include "dsgm_ext.h"
 #include "dsgm_fwd_impl.h"
 
 namespace dsgm {
