@@ -117,9 +117,15 @@ __device__ __forceinline__ StepRecord<Acc> step_core(Model<Acc>& s, const Acc x,
   const Acc dA = x - s.mA;
   const Acc qA = dA * dA;
   const Acc dC = x - s.mC;
-  const Acc qC = dC * dC;
+  Acc qC = dC * dC;
+  Acc tC = k.theta_s * s.vC;
+  // With double state the empty asm makes both operands of the C test opaque,
+  // so the compiler evaluates it in every lane instead of making it depend on
+  // the A test; that schedule measured faster in the double backward (about
+  // 8%) and equal in the double forward.
+  if constexpr (sizeof(Acc) == 8) asm volatile("" : "+v"(qC), "+v"(tC));
   const bool hitA = (qA < k.theta_s * s.vA) | (qA < k.ts_vf);
-  const bool hitC = (qC < k.theta_s * s.vC) | (qC < k.ts_vf);
+  const bool hitC = (qC < tC) | (qC < k.ts_vf);
 
   const int idx = hitA ? s.aA : (hitC ? s.aC : RESET_SLOT);
   const Acc m = hitA ? s.mA : s.mC;
