@@ -59,6 +59,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+VALU_PEAK_OPS = 256 * 64 * 2.4e9  # non-packed lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+# Algorithmic VALU ops per element (one pixel-frame), counted from the update
+# equations on the executed branch with the i.i.d. input's mix (A-match 40 %,
+# C-match 15 %, reset 45 %): A test 5, C test 5 when A misses, update 10
+# (8 flops, 2 integer) when a model matches, reset 3 moves, exchange test 1,
+# mask 6 -> about 22.  The other paths add their own arithmetic to that.
+OPS_STEP = 22
+OPS_ADJOINT = 36    # replay of the step (22) + reverse sweep of the matched update (14)
+OPS_PRE = 22 + 18 + 14   # + 5-tap row and column passes (9 each) + 3 x 3 median (14 min/max)
+OPS_WARP = 22 + 32 + 6 + 28 + 4   # + homography (2 divisions) + weights + 4 bilinear planes + nearest
+OPS_GRID4 = 10 + 22 / 16   # per pixel: block sum 1, V 3, mask 6; the step once per 16 pixels
+OPS_U8 = 22 + 12    # + the 8-bit storage rule on 4 values
 
 
 # the sources a kernel is compiled from: its translation unit and the headers
@@ -175,10 +188,23 @@ def timed_launches(call, n, steps, warmup, stream):
     return ms, sum(durs) / len(durs)
 
 
-def roof(alg_bytes, k_ms):
+def roof(alg_bytes, k_ms, elems=None, ops=None):
+    """HBM roofline of one launch (algorithmic bytes over its duration); with
+    the launch's elements and the algorithmic VALU ops per element, also both
+    ceilings in elements/s, the binding one and the fraction of it."""
     gbs = alg_bytes / (k_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if elems and ops:
+        rate = elems / (k_ms * 1e-3)
+        hbm_c = HBM_PEAK_GBS * 1e9 * elems / alg_bytes
+        valu_c = VALU_PEAK_OPS / ops
+        out["ceilings"] = {"bytes_per_element": round(alg_bytes / elems, 4), "ops_per_element": ops,
+                           "hbm_elements_per_s": round(hbm_c, 1),
+                           "valu_elements_per_s": round(valu_c, 1),
+                           "binding": "hbm" if hbm_c <= valu_c else "valu",
+                           "frac_of_binding": round(rate / min(hbm_c, valu_c), 4)}
+    return out
 
 
 # ---------------------------------------------------------------- legs
@@ -217,9 +243,9 @@ def leg_mixed(args, dsgm, sdev, torch):
     out = {
         "workload": "bf16 frames 1920x2560x500 seed 1, masks only",
         "fp32_state": {"elements_per_s": round(elems / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 4),
-                       "roofline": roof(elems * 3 + H * W * 36, float(sum(k32) / len(k32)))},
+                       "roofline": roof(elems * 3 + H * W * 36, float(sum(k32) / len(k32)), elems, OPS_STEP)},
         "fp64_state": {"elements_per_s": round(elems / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 4),
-                       "roofline": roof(elems * 3 + H * W * 68, float(sum(k64) / len(k64)))},
+                       "roofline": roof(elems * 3 + H * W * 68, float(sum(k64) / len(k64)), elems, OPS_STEP)},
         "speedup_fp32_over_fp64": round(ms64 / ms32, 3),
         "error_vs_fp64": {
             "mask_elements_differing_frac": float(diff.sum().item()) / elems,
@@ -251,7 +277,8 @@ def leg_video(args, dsgm, sdev, torch):
         masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
         ms, kk = timed(lambda: dsgm.dsgm_forward(fr, st, p, masks), steps, 1, stream)
         out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-                     "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)))}
+                     "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)),
+                                      elems, OPS_STEP)}
         del fr, st, masks
         torch.cuda.empty_cache()
     return out
@@ -276,7 +303,8 @@ def leg_filtered(args, dsgm, sdev, torch):
         masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
         ms, kk = timed(lambda: dsgm.dsgm_forward_filtered(fr, st, p, filt, masks), steps, 1, stream)
         out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-                     "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)))}
+                     "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)),
+                                      elems, OPS_PRE)}
         del fr, st, masks
         torch.cuda.empty_cache()
     return out
@@ -313,7 +341,7 @@ def leg_warped(args, dsgm, sdev, torch):
     out = {"workload": "1920x2560 x 100 frames, fp64, one launch per frame, per-frame homography",
            "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
            "kernel_ms_avg": round(k_ms, 5),
-           "roofline": roof(H * W * (8 + 1 + 34 + 34), k_ms)}
+           "roofline": roof(H * W * (8 + 1 + 34 + 34), k_ms, H * W, OPS_WARP)}
     del fr, a, b, masks, bufs
     torch.cuda.empty_cache()
     return out
@@ -334,7 +362,8 @@ def leg_grid(args, dsgm, sdev, torch):
     elems = T * H * W
     out = {"workload": "1920x2560x500 fp64, 4x4-pixel blocks, masks only",
            "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-           "roofline": roof(elems * 9 + (H // b) * (W // b) * 68, float(sum(kk) / len(kk)))}
+           "roofline": roof(elems * 9 + (H // b) * (W // b) * 68, float(sum(kk) / len(kk)),
+                       elems, OPS_GRID4)}
     del fr, st, masks
     torch.cuda.empty_cache()
     return out
@@ -362,13 +391,15 @@ def leg_streaming(args, dsgm, sdev, torch):
         dsgm.dsgm_state_init_from_frame(frames[0], st, p)
         masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
 
+        ops = OPS_U8 if name == "u8_as_run" else OPS_STEP
+
         def call(t):
             dsgm.dsgm_forward(frames[t:t + 1], st, p, masks[t:t + 1])
 
         ms, k_ms = timed_launches(call, T, steps, 1, stream)
         out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
                      "kernel_ms_avg": round(k_ms, 5),
-                     "roofline": roof(px * (in_b + 1 + 2 * st_bytes), k_ms),
+                     "roofline": roof(px * (in_b + 1 + 2 * st_bytes), k_ms, px, ops),
                      "bytes_per_element": in_b + 1 + 2 * st_bytes}
         del st, masks, frames
     del v
@@ -446,10 +477,10 @@ def leg_adjoint(args, dsgm, sdev, torch):
     out = {
         "workload": "fp32 frames and state 1920x2560x500 seed 2, bg on, K=32",
         "forward": {"elements_per_s": round(elems / (msf * 1e-3), 1), "ms_per_step": round(msf, 4),
-                    "roofline": roof(fwd_bytes, float(sum(kf) / len(kf))),
+                    "roofline": roof(fwd_bytes, float(sum(kf) / len(kf)), elems, OPS_STEP),
                     "checkpoint_bytes_written": ck_slots * px * 18},
         "backward": {"elements_per_s": round(elems / (msb * 1e-3), 1), "ms_per_step": round(msb, 4),
-                     "roofline": roof(bwd_bytes, float(sum(kb) / len(kb))),
+                     "roofline": roof(bwd_bytes, float(sum(kb) / len(kb)), elems, OPS_ADJOINT),
                      "checkpoint_bytes_read": ck_slots * px * 18},
         "grad_var_init": float(gvi.item()),
     }
@@ -494,10 +525,10 @@ def leg_largest(args, dsgm, sdev, torch):
     out = {"workload": "2160x3840x1344 fp32 frames, fp64 state, fp32 bg/gradients, K=32, seed 4",
            "resident_bytes": int(resident),
            "forward": {"elements_per_s": round(elems / (msf * 1e-3), 1), "ms_per_step": round(msf, 3),
-                       "roofline": roof(elems * 9 + px * 68, float(sum(kf) / len(kf))),
+                       "roofline": roof(elems * 9 + px * 68, float(sum(kf) / len(kf)), elems, OPS_STEP),
                        "checkpoint_bytes_written": ck_slots * px * 34},
            "backward": {"elements_per_s": round(elems / (msb * 1e-3), 1), "ms_per_step": round(msb, 3),
-                        "roofline": roof(elems * 12 + px * 40, float(sum(kb) / len(kb))),
+                        "roofline": roof(elems * 12 + px * 40, float(sum(kb) / len(kb)), elems, OPS_ADJOINT),
                         "checkpoint_bytes_read": ck_slots * px * 34},
            "grad_var_init": float(gvi.item())}
     del fr, st, st0, masks, bg, ck, gbg, gst, gx, gs0, gvi, ws
@@ -620,12 +651,12 @@ def leg_batched(args, dsgm, sdev, torch):
            "autotuned_pixels_per_lane": tuned["vector"],
            "autotune_candidates_ms": {str(c["vector"]): round(c["ms"], 3) for c in tuned["candidates"]},
            "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-           "roofline": roof(alg, float(sum(kk) / len(kk))),
+           "roofline": roof(alg, float(sum(kk) / len(kk)), elems, OPS_STEP),
            "fp64_form": {"workload": "the same 512 instances, fp64 frames (same values) and fp64 "
                                      "state, batched launches over %d chunks" % len(chunks),
                          "elements_per_s": round(elems / (ms64 * 1e-3), 1),
                          "ms_per_step": round(ms64, 4),
-                         "roofline": roof(elems * 9 + px * 68, sum(k64))},
+                         "roofline": roof(elems * 9 + px * 68, sum(k64), elems, OPS_STEP)},
            "speedup_mixed_over_fp64": round(ms64 / ms, 3),
            "error_vs_fp64": {"mask_elements_differing_frac": diff_elems / elems,
                              "pixels_with_any_mask_difference_frac": diff_px / px}}
@@ -686,7 +717,7 @@ def main():
     alg_bytes = elems * (8 + 1) + px * (4 * 8 + 2) * 2
     k_avg = float(np.mean(kern_ms))
     kernel = "fwd_kernel_f64_f64_p2"
-    rf = roof(alg_bytes, k_avg)
+    rf = roof(alg_bytes, k_avg, elems, OPS_STEP)
     rf.update({"traffic": load_traffic(kernel), "kernel": kernel, "kernel_ms_avg": round(k_avg, 4),
                "alg_bytes_per_launch": alg_bytes,
                "alg_bytes_per_element": round(alg_bytes / elems, 4)})
