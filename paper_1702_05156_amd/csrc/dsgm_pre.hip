@@ -83,13 +83,6 @@ __device__ __forceinline__ float tap<float>(float acc, float w, float x) {
   return __builtin_fmaf(w, x, acc);
 }
 
-// Logical tile of workgroup b: the hardware deals workgroups to the 8 XCDs
-// round-robin (b mod 8); XCD k gets the k-th contiguous share of the tiles.
-__device__ __forceinline__ int64_t tile_of(int64_t b, int64_t nb) {
-  const int64_t k = b % 8, i = b / 8, q = nb / 8, rem = nb % 8;
-  return k < rem ? k * (q + 1) + i : rem * (q + 1) + (k - rem) * q + i;
-}
-
 template <typename In, typename Acc, typename Io, int RG, bool MED>
 __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
   using G = Geo<RG, MED>;

@@ -35,6 +35,19 @@ __device__ __forceinline__ float bilin(float w00, float a, float w10, float b, f
   return __builtin_fmaf(w11, d, __builtin_fmaf(w01, c, __builtin_fmaf(w10, b, w00 * a)));
 }
 
+// two adjacent elements from one load; the address needs only element
+// alignment (the hardware serves multi-dword loads at dword alignment)
+template <typename Acc>
+struct Pair {
+  Acc x, y;
+};
+template <typename Acc>
+__device__ __forceinline__ Pair<Acc> ld_pair(const Acc* p) {
+  typedef Acc V __attribute__((ext_vector_type(2), aligned(sizeof(Acc))));
+  const V v = *reinterpret_cast<const V*>(p);
+  return Pair<Acc>{v.x, v.y};
+}
+
 template <typename In, typename Acc, typename Io>
 __global__ void __launch_bounds__(256) warp_kernel(const WarpArgs a) {
   __shared__ TableEntry<Acc> tbl[TABLE_SIZE];
@@ -42,7 +55,9 @@ __global__ void __launch_bounds__(256) warp_kernel(const WarpArgs a) {
   const StepConsts<Acc> k =
       make_consts<Acc>(a.theta_s, a.theta_d, a.var_init, a.var_floor, a.mask_floor);
 
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  // consecutive rows go to the same XCD, whose L2 then serves the source rows
+  // that neighbouring output rows share
+  const int64_t i = tile_of(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= a.H * a.W) return;  // no barrier follows
   const int64_t y = i / a.W, c = i - y * a.W;
   const int64_t fo = y * a.row_stride + c;  // frame / output offset
@@ -62,16 +77,32 @@ __global__ void __launch_bounds__(256) warp_kernel(const WarpArgs a) {
     const int64_t x1 = x0 + 1 < a.W ? x0 + 1 : a.W - 1, y1 = y0 + 1 < a.H ? y0 + 1 : a.H - 1;
     const Acc w00 = Acc((1.0 - fx) * (1.0 - fy)), w10 = Acc(fx * (1.0 - fy));
     const Acc w01 = Acc((1.0 - fx) * fy), w11 = Acc(fx * fy);
-    const int64_t i00 = y0 * a.W + x0, i10 = y0 * a.W + x1, i01 = y1 * a.W + x0,
-                  i11 = y1 * a.W + x1;
     const Acc* mA = static_cast<const Acc*>(a.src_mean_a);
     const Acc* vA = static_cast<const Acc*>(a.src_var_a);
     const Acc* mC = static_cast<const Acc*>(a.src_mean_c);
     const Acc* vC = static_cast<const Acc*>(a.src_var_c);
-    s.mA = bilin(w00, mA[i00], w10, mA[i10], w01, mA[i01], w11, mA[i11]);
-    s.vA = bilin(w00, vA[i00], w10, vA[i10], w01, vA[i01], w11, vA[i11]);
-    s.mC = bilin(w00, mC[i00], w10, mC[i10], w01, mC[i01], w11, mC[i11]);
-    s.vC = bilin(w00, vC[i00], w10, vC[i10], w01, vC[i01], w11, vC[i11]);
+    if (a.W >= 2) {
+      // each row's two neighbours come from one pair load at columns xa, xa+1
+      // (xa = x0 except on the last column, where both neighbours are x0)
+      const int64_t xa = x0 < a.W - 1 ? x0 : a.W - 2;
+      const bool lo = xa == x0;
+      const int64_t r0 = y0 * a.W + xa, r1 = y1 * a.W + xa;
+      auto gather = [&](const Acc* p) {
+        const Pair<Acc> t = ld_pair(p + r0), b = ld_pair(p + r1);
+        return bilin(w00, lo ? t.x : t.y, w10, t.y, w01, lo ? b.x : b.y, w11, b.y);
+      };
+      s.mA = gather(mA);
+      s.vA = gather(vA);
+      s.mC = gather(mC);
+      s.vC = gather(vC);
+    } else {
+      const int64_t i00 = y0 * a.W + x0, i10 = y0 * a.W + x1, i01 = y1 * a.W + x0,
+                    i11 = y1 * a.W + x1;
+      s.mA = bilin(w00, mA[i00], w10, mA[i10], w01, mA[i01], w11, mA[i11]);
+      s.vA = bilin(w00, vA[i00], w10, vA[i10], w01, vA[i01], w11, vA[i11]);
+      s.mC = bilin(w00, mC[i00], w10, mC[i10], w01, mC[i01], w11, mC[i11]);
+      s.vC = bilin(w00, vC[i00], w10, vC[i10], w01, vC[i01], w11, vC[i11]);
+    }
     int64_t xn = int64_t(floor(qx + 0.5)), yn = int64_t(floor(qy + 0.5));
     xn = xn > a.W - 1 ? a.W - 1 : xn;
     yn = yn > a.H - 1 ? a.H - 1 : yn;

@@ -36,7 +36,7 @@ def _oracle_step(st_host, x, m, p, H, W):
 
 
 @pytest.mark.parametrize("name", ["identity", "shift", "subpixel", "rigid", "perspective"])
-@pytest.mark.parametrize("H,W", [(37, 61), (64, 256)])
+@pytest.mark.parametrize("H,W", [(37, 61), (64, 256), (1, 5), (4, 1), (2, 2)])
 def test_warped_step_f64_bit_exact(name, H, W):
     p = dsgm.dsgm_params_default(2.0)
     m = _maps(H, W)[name]
