@@ -10,7 +10,8 @@
 // Decomposition: one lane per block for all T frames, the block's models in
 // registers; per frame the lane reads the block's b rows (one vector load per
 // row when the block is whole and aligned), keeps the b*b intensities in
-// registers for the V and mask passes, and writes b mask rows.  Neighbouring
+// registers for the V and mask passes, and writes b mask rows; the next
+// frame's rows are loaded while the current one is processed.  Neighbouring
 // lanes own neighbouring blocks, so every row access is contiguous across the
 // wavefront.  With FP64 state the block sum (row-major from 0), the division
 // by |G| and the update follow the order of a scalar evaluation.
@@ -52,9 +53,9 @@ __global__ void __launch_bounds__(256) grid_kernel(const GridArgs a) {
 
   const In* frames = static_cast<const In*>(a.frames);
   const int64_t base = y0 * a.row_stride + x0;
-  for (int64_t t = 0; t < a.T; ++t) {
+  // the block's b x b intensities of frame t
+  auto load = [&](int64_t t, Acc (&I)[B][B]) {
     const int64_t o = t * a.frame_stride + base;
-    Acc I[B][B];
     if (vec) {
 #pragma unroll
       for (int r = 0; r < B; ++r) {
@@ -70,6 +71,9 @@ __global__ void __launch_bounds__(256) grid_kernel(const GridArgs a) {
           I[r][c] = (r < rows && c < cols) ? to_acc<In, Acc>(frames[o + r * a.row_stride + c])
                                            : Acc(0);
     }
+  };
+  auto frame = [&](int64_t t, const Acc (&I)[B][B]) {
+    const int64_t o = t * a.frame_stride + base;
     // block mean, row-major from 0 (missing pixels of an edge block are skipped)
     Acc sum = Acc(0);
 #pragma unroll
@@ -139,7 +143,20 @@ __global__ void __launch_bounds__(256) grid_kernel(const GridArgs a) {
       a.codes[t * a.Hb * a.Wb + blk] = uint8_t(code);
     }
     if (a.bg) static_cast<Io*>(a.bg)[t * a.Hb * a.Wb + blk] = Io(s.mA);
+  };
+  // two frame buffers: the next frame's loads are in flight while this one
+  // is processed
+  Acc I0[B][B], I1[B][B];
+  const int64_t T = a.T;
+  if (T > 0) load(0, I0);
+  int64_t t = 0;
+  for (; t + 1 < T; t += 2) {
+    load(t + 1, I1);
+    frame(t, I0);
+    if (t + 2 < T) load(t + 2, I0);
+    frame(t + 1, I1);
   }
+  if (t < T) frame(t, I0);
   static_cast<Acc*>(a.mean_a)[blk] = s.mA;
   static_cast<Acc*>(a.var_a)[blk] = s.vA;
   static_cast<Acc*>(a.mean_c)[blk] = s.mC;
