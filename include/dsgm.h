@@ -25,7 +25,8 @@
  *   - "accumulation type" below means the state type of dsgm_acc; "array type"
  *     the type of bg and of the gradient arrays (FP32 for F64_IO32).
  *   - Every call is asynchronous on `stream` (NULL = the null stream) and never
- *     synchronizes.  Arguments are validated on the host before any HIP call; a
+ *     synchronizes, except the set-up calls dsgm_plan_batched and
+ *     dsgm_autotune, which say so.  Arguments are validated on the host before any HIP call; a
  *     kernel fault surfaces as a HIP error of a later call or synchronization.
  *   - Every call returns a dsgm_status; nothing is thrown across the ABI.  On
  *     failure dsgm_last_error() (per thread) describes it.
@@ -355,6 +356,49 @@ const char* dsgm_last_error(void);
 
 /* ABI version: major*10000 + minor*100 + patch */
 int dsgm_version(void);
+
+/* Flags of the launch-shape tuner: the optional outputs of the calls to tune */
+typedef enum {
+  DSGM_TUNE_BG = 1,      /* bg written */
+  DSGM_TUNE_CKPT = 2,    /* checkpoints written */
+  DSGM_TUNE_PRINTED = 4  /* params.mask_rule = DSGM_MASK_PRINTED */
+} dsgm_tune_flags;
+
+/* bytes of the workspace dsgm_autotune needs for these arguments (0 on bad
+ * arguments or an empty problem) */
+size_t dsgm_autotune_bytes(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape,
+                           int32_t flags);
+
+/*
+ * Launch-shape tuner of dsgm_forward (a set-up call, not for the hot loop).
+ * Sec. 3.4 measures how the threads per block change the GPU time; this call
+ * makes that measurement for the caller's problem: it times dsgm_forward on
+ * min(T, 64) frames of H x W independent uniform intensities (dense layout,
+ * default parameters for the frame type's range, the outputs that `flags`
+ * names) for every workgroup size 64, 128, 256 and every pixels-per-lane width
+ * 1, 2, 4 that W allows, each from the same initial state, and keeps the
+ * fastest in a process-wide table under the key (in_dtype, acc, H, W, flags).
+ * Later dsgm_forward calls whose arguments have that key launch with the
+ * chosen shape (a width their strides or alignments do not allow is replaced
+ * as usual); dsgm_set_launch overrides the table.  Results never depend on the
+ * launch shape.
+ *   workspace  device, 256-byte aligned, dsgm_autotune_bytes bytes, owned by
+ *              the caller (free to reuse once the call returns)
+ *   chosen     NULL or (host) 2 int32: the chosen block size and width
+ *              ({0, 0} for an empty problem, which tunes nothing)
+ * Runs its kernels on `stream` and synchronizes it.  The 8-bit as-run pair
+ * accepts DSGM_TUNE_PRINTED only (DSGM_E_UNSUPPORTED otherwise).
+ */
+int dsgm_autotune(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape, int32_t flags,
+                  void* workspace, size_t ws_bytes, int32_t* chosen /* host */, hipStream_t stream);
+
+/* the tuner's table entry for these arguments: chosen (host, 2 int32) =
+ * {block, width}, or {0, 0} if they were not tuned; no HIP call */
+int dsgm_autotune_lookup(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape, int32_t flags,
+                         int32_t* chosen /* host */);
+
+/* empty the tuner's table (later calls use the default launch shapes) */
+int dsgm_autotune_clear(void);
 
 /*
  * Launch-shape override for tuning and tests (process-wide): `block` threads

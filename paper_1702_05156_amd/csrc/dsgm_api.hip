@@ -7,6 +7,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "dsgm.h"
@@ -109,6 +112,32 @@ int check_shape(const dsgm_shape& s, size_t max_elem_bytes) {
 
 int g_block_override = 0;  // set by dsgm_set_launch (tuning)
 int g_vector_override = 0;
+
+// Launch shapes chosen by dsgm_autotune, per (frame type, state type, H, W,
+// output flags); dsgm_forward looks its arguments up here.
+struct TuneKey {
+  int in_dtype, acc;
+  int64_t H, W;
+  int flags;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(in_dtype, acc, H, W, flags) < std::tie(o.in_dtype, o.acc, o.H, o.W, o.flags);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;  // -> (block, pixels per lane)
+
+bool tune_lookup(const TuneKey& k, int* block, int* vector) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const auto it = g_tune.find(k);
+  if (it == g_tune.end()) return false;
+  *block = it->second.first;
+  *vector = it->second.second;
+  return true;
+}
+
+constexpr int kTuneFlags = DSGM_TUNE_BG | DSGM_TUNE_CKPT | DSGM_TUNE_PRINTED;
+constexpr int kTuneFrames = 64;  // frames per timed call: the cost per frame is flat beyond
+constexpr int kTuneCkptEvery = 32;
 
 // Preferred pixels per lane, measured on MI355X at 1920x2560x500: FP64 and
 // FP32 state run fastest with 2 (more waves per SIMD), BF16 frames with 4
@@ -283,10 +312,16 @@ int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_
   return ok();
 }
 
-int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
+}  // extern "C"
+
+namespace {
+
+// dsgm_forward with an optional forced launch shape (block, pixels per lane;
+// 0 = the usual choice), which the tuner uses to time its candidates
+int forward_impl(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
                  const dsgm_params* params, dsgm_state* state, uint8_t* masks, void* bg,
                  void* ckpt, size_t ckpt_bytes, int32_t ckpt_every, uint8_t* codes,
-                 hipStream_t stream) {
+                 hipStream_t stream, int force_block, int force_vector) {
   int rc;
   if ((rc = check_types_u8(in_dtype, acc))) return rc;
   if ((rc = check_params(params))) return rc;
@@ -316,10 +351,22 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
       return fail(DSGM_E_ALIGN, "pointer argument %d is not aligned to %zu bytes", i, need);
   }
   const int widest = pick_vector(shape, ptrs, elem, 10);
+  // pixels per lane the layout allows: sizes, strides and every base pointer,
+  // the checkpoint's included
+  auto legal = [&](int v) { return widest % v == 0 && (!ckpt || aligned(ckpt, ae * v)); };
   int P = std::min(widest, preferred_vector(in_dtype, acc));
-  if (ckpt && !aligned(ckpt, ae * P)) P = 1;
+  if (!legal(P)) P = 1;
   if (as_run) P = widest;  // four one-byte pixels per lane when the layout allows
-  if (g_vector_override && widest % g_vector_override == 0) P = g_vector_override;
+  int block = 256;
+  const int tflags = (bg ? DSGM_TUNE_BG : 0) | (ckpt ? DSGM_TUNE_CKPT : 0) |
+                     (params->mask_rule == DSGM_MASK_PRINTED ? DSGM_TUNE_PRINTED : 0);
+  int tb = force_block, tv = force_vector;
+  if (!tb && !g_block_override && !g_vector_override)
+    tune_lookup(TuneKey{in_dtype, acc, shape.H, shape.W, tflags}, &tb, &tv);
+  if (tb) block = tb;
+  if (tv && legal(tv)) P = tv;
+  if (g_vector_override && legal(g_vector_override)) P = g_vector_override;
+  if (g_block_override) block = g_block_override;
   if (codes && !as_run) P = 1;  // the decision-code (debug) variants run one pixel per lane
 
   dsgm::FwdArgs a;
@@ -354,13 +401,183 @@ int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   a.age_max = params->age_max;
   a.weight_rule = params->weight_rule;
   a.mask_rule = params->mask_rule;
-  const int block = g_block_override ? g_block_override : 256;
   const int flags = (bg ? dsgm::FWD_BG : 0) | (codes ? dsgm::FWD_CODES : 0) |
                     (ckpt ? dsgm::FWD_CKPT : 0) |
                     (params->mask_rule == DSGM_MASK_PRINTED ? dsgm::FWD_PRINTED : 0);
   hipError_t e = as_run ? dsgm::launch_fwd_u8(a, P, flags, block, stream)
                         : dsgm::launch_forward(a, in_dtype, acc, P, flags, block, stream);
   if (e != hipSuccess) return hip_fail(e, "dsgm_forward launch");
+  return ok();
+}
+
+// the tuner's buffers, carved from one workspace in 256-byte-aligned pieces
+struct TuneLayout {
+  dsgm_shape shape;
+  int64_t frames = 0, masks = 0, bg = 0, ckpt = 0, planes = 0, ages = 0, bytes = 0;
+  size_t ckpt_bytes = 0;
+};
+
+TuneLayout tune_layout(int in_dtype, int acc, const dsgm_shape& s, int flags) {
+  TuneLayout L;
+  const int64_t T = std::min<int64_t>(s.T, kTuneFrames), px = s.H * s.W;
+  L.shape = dsgm_shape{T, s.H, s.W, s.W, px};
+  const int64_t n = T * px;
+  int64_t off = 0;
+  auto take = [&](int64_t b) { const int64_t o = off; off += pad256(b); return o; };
+  L.frames = take(n * int64_t(in_size(in_dtype)));
+  L.masks = take(n);
+  if (flags & DSGM_TUNE_BG) L.bg = take(n * int64_t(io_size(acc)));
+  if (flags & DSGM_TUNE_CKPT) {
+    L.ckpt_bytes = dsgm_ckpt_bytes(L.shape, dsgm_acc(acc), kTuneCkptEvery);
+    L.ckpt = take(int64_t(L.ckpt_bytes));
+  }
+  L.planes = take(4 * pad256(px * int64_t(acc_size(acc))));
+  L.ages = take(2 * pad256(px));
+  L.bytes = off;
+  return L;
+}
+
+int check_tune_args(int in_dtype, int acc, const dsgm_shape& shape, int flags) {
+  int rc;
+  if ((rc = check_types_u8(in_dtype, acc))) return rc;
+  if (flags & ~kTuneFlags) return fail(DSGM_E_ARG, "flags = %d: unknown bits", flags);
+  if (acc == DSGM_ACC_U8 && (flags & (DSGM_TUNE_BG | DSGM_TUNE_CKPT)))
+    return fail(DSGM_E_UNSUPPORTED, "the 8-bit as-run model has no bg or checkpoint output");
+  const size_t ie = in_size(in_dtype), oe = io_size(acc);
+  const dsgm_shape dense{std::min<int64_t>(shape.T, kTuneFrames), shape.H, shape.W, shape.W,
+                         shape.H * shape.W};
+  if (shape.T < 0 || shape.H < 0 || shape.W < 0)
+    return fail(DSGM_E_SHAPE, "negative size T=%lld H=%lld W=%lld", (long long)shape.T,
+                (long long)shape.H, (long long)shape.W);
+  return check_shape(dense, ie > oe ? ie : oe);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dsgm_forward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
+                 const dsgm_params* params, dsgm_state* state, uint8_t* masks, void* bg,
+                 void* ckpt, size_t ckpt_bytes, int32_t ckpt_every, uint8_t* codes,
+                 hipStream_t stream) {
+  return forward_impl(frames, in_dtype, shape, acc, params, state, masks, bg, ckpt, ckpt_bytes,
+                      ckpt_every, codes, stream, 0, 0);
+}
+
+size_t dsgm_autotune_bytes(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape,
+                           int32_t flags) {
+  if (check_tune_args(in_dtype, acc, shape, flags)) return 0;
+  if (shape.T == 0 || shape.H * shape.W == 0) return 0;
+  return size_t(tune_layout(in_dtype, acc, shape, flags).bytes);
+}
+
+int dsgm_autotune(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape, int32_t flags,
+                  void* workspace, size_t ws_bytes, int32_t* chosen, hipStream_t stream) {
+  int rc;
+  if (chosen) chosen[0] = chosen[1] = 0;
+  if ((rc = check_tune_args(in_dtype, acc, shape, flags))) return rc;
+  if (shape.T == 0 || shape.H * shape.W == 0) return ok();
+  const TuneLayout L = tune_layout(in_dtype, acc, shape, flags);
+  if (!workspace) return fail(DSGM_E_ARG, "workspace is NULL");
+  if (!aligned(workspace, 256)) return fail(DSGM_E_ALIGN, "workspace is not 256-byte aligned");
+  if (ws_bytes < size_t(L.bytes))
+    return fail(DSGM_E_WORKSPACE, "workspace of %zu bytes, %lld needed", ws_bytes,
+                (long long)L.bytes);
+  char* w = static_cast<char*>(workspace);
+  const int64_t px = shape.H * shape.W;
+  void* frames = w + L.frames;
+  uint8_t* masks = reinterpret_cast<uint8_t*>(w + L.masks);
+  void* bg = (flags & DSGM_TUNE_BG) ? w + L.bg : nullptr;
+  void* ckpt = (flags & DSGM_TUNE_CKPT) ? w + L.ckpt : nullptr;
+  const int64_t fplane = pad256(px * int64_t(acc_size(acc)));
+  dsgm_state st;
+  st.mean_a = w + L.planes;
+  st.var_a = w + L.planes + fplane;
+  st.mean_c = w + L.planes + 2 * fplane;
+  st.var_c = w + L.planes + 3 * fplane;
+  st.age_a = reinterpret_cast<uint8_t*>(w + L.ages);
+  st.age_c = reinterpret_cast<uint8_t*>(w + L.ages + pad256(px));
+  dsgm_params p;
+  dsgm_params_default(&p, in_dtype == DSGM_IN_U8 ? 255.0 : 2.0,
+                      (flags & DSGM_TUNE_PRINTED) ? DSGM_MASK_PRINTED : DSGM_MASK_VARIANCE);
+
+  hipError_t e = dsgm::launch_tune_fill(frames, in_dtype, L.shape.T * px, 1, stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_autotune fill");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "dsgm_autotune event");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    hipEventDestroy(e0);
+    return hip_fail(e, "dsgm_autotune event");
+  }
+  // two rounds over the candidates, each candidate's time the better of its
+  // two (interleaving keeps clock and cache drift from favouring one)
+  const int blocks[3] = {64, 128, 256}, vectors[3] = {1, 2, 4};
+  constexpr int kReps = 4, kRounds = 2;
+  float best_ms[9];
+  for (int c = 0; c < 9; ++c) best_ms[c] = -1.f;
+  rc = DSGM_OK;
+  for (int round = 0; round < kRounds && rc == DSGM_OK; ++round) {
+    for (int c = 0; c < 9 && rc == DSGM_OK; ++c) {
+      const int b = blocks[c / 3], v = vectors[c % 3];
+      if (shape.W % v) continue;
+      // every candidate starts from the same state; one untimed call warms up
+      if ((rc = dsgm_state_init_from_frame(frames, in_dtype, L.shape, acc, &p, &st, stream)))
+        break;
+      for (int r = 0; r <= kReps && rc == DSGM_OK; ++r) {
+        if (r == 1 && (e = hipEventRecord(e0, stream)) != hipSuccess) {
+          rc = hip_fail(e, "dsgm_autotune event record");
+          break;
+        }
+        rc = forward_impl(frames, in_dtype, L.shape, acc, &p, &st, masks, bg, ckpt, L.ckpt_bytes,
+                          kTuneCkptEvery, nullptr, stream, b, v);
+      }
+      if (rc != DSGM_OK) break;
+      float ms = 0.f;
+      if ((e = hipEventRecord(e1, stream)) != hipSuccess ||
+          (e = hipEventSynchronize(e1)) != hipSuccess ||
+          (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+        rc = hip_fail(e, "dsgm_autotune timing");
+        break;
+      }
+      if (best_ms[c] < 0.f || ms < best_ms[c]) best_ms[c] = ms;
+    }
+  }
+  int best = -1;
+  for (int c = 0; c < 9; ++c)
+    if (best_ms[c] >= 0.f && (best < 0 || best_ms[c] < best_ms[best])) best = c;
+  const int best_block = best >= 0 ? blocks[best / 3] : 256;
+  const int best_vector = best >= 0 ? vectors[best % 3] : 1;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != DSGM_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[TuneKey{in_dtype, acc, shape.H, shape.W, flags}] = {best_block, best_vector};
+  }
+  if (chosen) {
+    chosen[0] = best_block;
+    chosen[1] = best_vector;
+  }
+  return ok();
+}
+
+int dsgm_autotune_lookup(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape, int32_t flags,
+                         int32_t* chosen) {
+  int rc;
+  if (!chosen) return fail(DSGM_E_ARG, "chosen is NULL");
+  chosen[0] = chosen[1] = 0;
+  if ((rc = check_tune_args(in_dtype, acc, shape, flags))) return rc;
+  int b = 0, v = 0;
+  if (tune_lookup(TuneKey{in_dtype, acc, shape.H, shape.W, flags}, &b, &v)) {
+    chosen[0] = b;
+    chosen[1] = v;
+  }
+  return ok();
+}
+
+int dsgm_autotune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
   return ok();
 }
 

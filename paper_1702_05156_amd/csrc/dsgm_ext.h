@@ -84,4 +84,18 @@ struct GridArgs {
 
 hipError_t launch_grid(const GridArgs& a, int in_dtype, int acc, int b, hipStream_t stream);
 
+// Fill n elements of the given frame type (0 F64, 1 F32, 2 BF16, 3 U8) with
+// independent uniform intensities, a function of (seed, index) (dsgm_tune.hip).
+hipError_t launch_tune_fill(void* out, int in_dtype, int64_t n, uint64_t seed,
+                            hipStream_t stream);
+
+// Logical tile of workgroup b of nb: the hardware deals workgroups to the 8
+// XCDs round-robin (b mod 8), each XCD with its own L2; this bijection gives
+// XCD k the k-th contiguous share of the tiles, so tiles that share input rows
+// (stencil halos, the source rows of a warp) meet in the same L2.
+__device__ __forceinline__ int64_t tile_of(int64_t b, int64_t nb) {
+  const int64_t k = b % 8, i = b / 8, q = nb / 8, rem = nb % 8;
+  return k < rem ? k * (q + 1) + i : rem * (q + 1) + (k - rem) * q + i;
+}
+
 }  // namespace dsgm

@@ -128,10 +128,17 @@ def _load():
     lib.dsgm_status_string.restype = ctypes.c_char_p
     lib.dsgm_last_error.restype = ctypes.c_char_p
     lib.dsgm_set_launch.argtypes = [i32, i32]
+    lib.dsgm_autotune_bytes.argtypes = [i32, i32, Shape, i32]
+    lib.dsgm_autotune_bytes.restype = ctypes.c_size_t
+    lib.dsgm_autotune.argtypes = [i32, i32, Shape, i32, vp, ctypes.c_size_t,
+                                  ctypes.POINTER(ctypes.c_int32), vp]
+    lib.dsgm_autotune_lookup.argtypes = [i32, i32, Shape, i32, ctypes.POINTER(ctypes.c_int32)]
+    lib.dsgm_autotune_clear.argtypes = []
     for f in ("dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
               "dsgm_backward", "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_version",
               "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
-              "dsgm_forward_warped", "dsgm_forward_grid"):
+              "dsgm_forward_warped", "dsgm_forward_grid", "dsgm_autotune",
+              "dsgm_autotune_lookup", "dsgm_autotune_clear"):
         getattr(lib, f).restype = ctypes.c_int
     del i64
     return lib
@@ -144,7 +151,8 @@ EXPORTS = ["dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
            "dsgm_ckpt_bytes", "dsgm_workspace_bytes", "dsgm_backward", "dsgm_batch_plan_bytes",
            "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_status_string", "dsgm_last_error",
            "dsgm_version", "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
-           "dsgm_forward_warped", "dsgm_forward_grid"]
+           "dsgm_forward_warped", "dsgm_forward_grid", "dsgm_autotune_bytes", "dsgm_autotune",
+           "dsgm_autotune_lookup", "dsgm_autotune_clear"]
 
 
 def _check(fn: str, rc: int):
@@ -173,6 +181,40 @@ def dsgm_version() -> int:
 
 def dsgm_set_launch(block: int = 0, vector: int = 0) -> None:
     _check("dsgm_set_launch", lib.dsgm_set_launch(block, vector))
+
+
+TUNE_BG, TUNE_CKPT, TUNE_PRINTED = 1, 2, 4
+
+
+def _tune_shape(T: int, H: int, W: int) -> Shape:
+    return Shape(int(T), int(H), int(W), int(W), int(H) * int(W))
+
+
+def dsgm_autotune_bytes(in_dtype: int, acc: int, T: int, H: int, W: int, flags: int = 0) -> int:
+    return int(lib.dsgm_autotune_bytes(in_dtype, acc, _tune_shape(T, H, W), flags))
+
+
+def dsgm_autotune(in_dtype: int, acc: int, T: int, H: int, W: int, flags: int = 0) -> tuple:
+    """Time dsgm_forward's launch shapes on a synthetic T x H x W problem and keep
+    the fastest for later calls with these types, sizes and outputs; returns
+    (block, pixels per lane).  Allocates its workspace with torch."""
+    n = dsgm_autotune_bytes(in_dtype, acc, T, H, W, flags)
+    ws = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+    chosen = (ctypes.c_int32 * 2)()
+    _check("dsgm_autotune", lib.dsgm_autotune(in_dtype, acc, _tune_shape(T, H, W), flags,
+                                              _ptr(ws), n, chosen, _stream()))
+    return int(chosen[0]), int(chosen[1])
+
+
+def dsgm_autotune_lookup(in_dtype: int, acc: int, T: int, H: int, W: int, flags: int = 0) -> tuple:
+    chosen = (ctypes.c_int32 * 2)()
+    _check("dsgm_autotune_lookup",
+           lib.dsgm_autotune_lookup(in_dtype, acc, _tune_shape(T, H, W), flags, chosen))
+    return int(chosen[0]), int(chosen[1])
+
+
+def dsgm_autotune_clear() -> None:
+    _check("dsgm_autotune_clear", lib.dsgm_autotune_clear())
 
 
 # ------------------------------------------------------------------ state

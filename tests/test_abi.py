@@ -284,3 +284,38 @@ def test_empty_problems_of_the_extensions_need_no_gpu():
     rc = lib.dsgm_backward(1 << 20, 3, dsgm.Shape(2, 8, 8, 8, 64), 3, ctypes.byref(p8), None, 0,
                            1, None, None, 1 << 20, None, None, None, 0, None)
     assert rc == -3
+
+
+def test_autotune_arguments_rejected_before_any_hip_call():
+    S = dsgm._tune_shape
+    i32x2 = ctypes.c_int32 * 2
+    chosen = i32x2(7, 7)
+    # sizes of the tuner's workspace: dense min(T, 64) frames + outputs + state
+    n = dsgm.dsgm_autotune_bytes(dsgm.IN_F64, dsgm.ACC_F64, 500, 48, 64)
+    assert n >= 64 * 48 * 64 * (8 + 1) + 48 * 64 * (4 * 8 + 2)
+    assert dsgm.dsgm_autotune_bytes(dsgm.IN_F64, dsgm.ACC_F64, 500, 48, 64, dsgm.TUNE_BG) > n
+    assert dsgm.dsgm_autotune_bytes(dsgm.IN_F64, dsgm.ACC_F64, 0, 48, 64) == 0
+    assert dsgm.dsgm_autotune_bytes(dsgm.IN_F64, dsgm.ACC_F32, 5, 48, 64) == 0  # bad pair
+    # empty problem: nothing to tune, chosen = {0, 0}
+    assert lib.dsgm_autotune(dsgm.IN_F32, dsgm.ACC_F32, S(0, 8, 8), 0, None, 0, chosen, None) == 0
+    assert list(chosen) == [0, 0]
+    bad = [
+        ((dsgm.IN_F64, dsgm.ACC_F32, S(4, 8, 8), 0, None, 0), -3),
+        ((9, dsgm.ACC_F32, S(4, 8, 8), 0, None, 0), -3),
+        ((dsgm.IN_F32, dsgm.ACC_F32, S(4, 8, 8), 8, None, 0), -1),
+        ((dsgm.IN_U8, dsgm.ACC_U8, S(4, 8, 8), dsgm.TUNE_CKPT, None, 0), -7),
+        ((dsgm.IN_F32, dsgm.ACC_F32, S(-1, 8, 8), 0, None, 0), -2),
+        ((dsgm.IN_F32, dsgm.ACC_F32, S(4, 8, 8), 0, None, 0), -1),      # no workspace
+        ((dsgm.IN_F32, dsgm.ACC_F32, S(4, 8, 8), 0, ctypes.c_void_p(256), 16),
+         -5),
+        ((dsgm.IN_F32, dsgm.ACC_F32, S(4, 8, 8), 0, ctypes.c_void_p(260), 1 << 20),
+         -4),
+    ]
+    for args, want in bad:
+        assert lib.dsgm_autotune(*args, chosen, None) == want, (args, lib.dsgm_last_error())
+    # the table: empty until a tuning run fills it; lookups need no GPU
+    assert dsgm.dsgm_autotune_clear() is None
+    assert dsgm.dsgm_autotune_lookup(dsgm.IN_F64, dsgm.ACC_F64, 500, 1920, 2560) == (0, 0)
+    assert lib.dsgm_autotune_lookup(dsgm.IN_F64, dsgm.ACC_F64, S(5, 8, 8), 0, None) == -1
+    with pytest.raises(dsgm.DSGMError):
+        dsgm.dsgm_autotune_lookup(dsgm.IN_F64, dsgm.ACC_F64, 5, 8, 8, 16)

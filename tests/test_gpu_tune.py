@@ -61,3 +61,78 @@ def test_tune_batched_picks_a_width_and_results_do_not_depend_on_it(tmp_path, mo
         assert torch.equal(ma, mb)
         for u, v in zip(sa.planes(), sb.planes()):
             assert torch.equal(u, v)
+
+
+def _same_forward(fr, st, p, **kw):
+    """dsgm.forward with the tuner's table as it is and with the table empty:
+    every output and the final state must be identical."""
+    a_st = st.clone()
+    a = dsgm.forward(fr, a_st, p, **kw)
+    torch.cuda.synchronize()
+    return a, a_st
+
+
+@pytest.mark.parametrize("in_dtype,acc_dtype,acc,flags,W", [
+    (torch.float32, torch.float32, dsgm.ACC_F32, 0, 512),
+    (torch.float64, torch.float64, dsgm.ACC_F64, dsgm.TUNE_BG | dsgm.TUNE_CKPT, 256),
+    (torch.bfloat16, torch.float32, dsgm.ACC_F32, dsgm.TUNE_BG, 260),
+])
+def test_native_autotune_chooses_and_applies(in_dtype, acc_dtype, acc, flags, W):
+    """dsgm_autotune times the launch shapes, records the fastest under the key
+    of these arguments, and dsgm_forward then launches with it: every output,
+    the checkpoints and the final state equal those of the default shape."""
+    T, H = 40, 48
+    dsgm.dsgm_autotune_clear()
+    in_code = dsgm._IN_DTYPES[in_dtype]
+    chosen = dsgm.dsgm_autotune(in_code, acc, T, H, W, flags)
+    assert chosen[0] in (64, 128, 256) and chosen[1] in (1, 2, 4) and W % chosen[1] == 0
+    assert dsgm.dsgm_autotune_lookup(in_code, acc, T, H, W, flags) == chosen
+    assert dsgm.dsgm_autotune_lookup(in_code, acc, T, H, W + 4, flags) == (0, 0)
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(43, T, H, W, in_dtype, acc_dtype)
+    kw = dict(bg=bool(flags & dsgm.TUNE_BG), ckpt_every=8 if flags & dsgm.TUNE_CKPT else 0)
+    tuned, tuned_st = _same_forward(fr, st, p, **kw)
+    dsgm.dsgm_autotune_clear()
+    ref, ref_st = _same_forward(fr, st, p, **kw)
+    for k in ref:
+        assert torch.equal(tuned[k], ref[k]), k
+    for a, b in zip(tuned_st.planes(), ref_st.planes()):
+        assert torch.equal(a, b)
+
+
+def test_native_autotune_width_the_layout_forbids_is_replaced():
+    """A tuned width that a call's strides do not allow (odd row stride) is
+    replaced by one they allow; the results are those of the default shape."""
+    T, H, W = 24, 40, 256
+    dsgm.dsgm_autotune_clear()
+    chosen = dsgm.dsgm_autotune(dsgm.IN_F32, dsgm.ACC_F32, T, H, W)
+    assert chosen[1] in (1, 2, 4)
+    p = dsgm.dsgm_params_default(2.0)
+    big, st = G.device_case(44, T, H, W + 1, torch.float32, torch.float32)
+    fr = big[:, :, :W]  # row stride W + 1
+    st = dsgm.State(*(t[:, :W].contiguous() for t in st.planes()))
+    tuned, tuned_st = _same_forward(fr, st, p)
+    dsgm.dsgm_autotune_clear()
+    ref, ref_st = _same_forward(fr, st, p)
+    assert torch.equal(tuned["masks"], ref["masks"])
+    for a, b in zip(tuned_st.planes(), ref_st.planes()):
+        assert torch.equal(a, b)
+
+
+def test_native_autotune_u8_and_empty():
+    T, H, W = 16, 32, 128
+    dsgm.dsgm_autotune_clear()
+    assert dsgm.dsgm_autotune(dsgm.IN_U8, dsgm.ACC_U8, 0, H, W) == (0, 0)
+    chosen = dsgm.dsgm_autotune(dsgm.IN_U8, dsgm.ACC_U8, T, H, W, dsgm.TUNE_PRINTED)
+    assert chosen[0] in (64, 128, 256) and chosen[1] in (1, 2, 4)
+    p = dsgm.dsgm_params_default(255.0, dsgm.MASK_PRINTED)
+    p.weight_rule = dsgm.WEIGHT_APPENDIX
+    fr = (sdev.frames(45, T, H, W, torch.float32) * 127.5 + 127.5).to(torch.uint8)
+    st = dsgm.State.empty(H, W, torch.uint8)
+    dsgm.dsgm_state_init_from_frame(fr[0], st, p)
+    tuned, tuned_st = _same_forward(fr, st, p)
+    dsgm.dsgm_autotune_clear()
+    ref, ref_st = _same_forward(fr, st, p)
+    assert torch.equal(tuned["masks"], ref["masks"])
+    for a, b in zip(tuned_st.planes(), ref_st.planes()):
+        assert torch.equal(a, b)
