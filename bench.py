@@ -59,7 +59,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-VALU_PEAK_OPS = 256 * 64 * 2.4e9  # non-packed lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+# VALU lane-ops/s from the published vector peaks (an FMA counted as one op):
+# FP64 78.6 TFLOP/s -> 39.3 T, i.e. 64 lanes per CU per clock at 2.4 GHz on 256
+# CUs; FP32 157.3 TFLOP/s -> 78.6 T (32-bit operations issue at twice the FP64
+# rate, which the FP32 forward's own instruction rate confirms).
+VALU_PEAK_F64 = 256 * 64 * 2.4e9
+VALU_PEAK_F32 = 256 * 128 * 2.4e9
 
 # Algorithmic VALU ops per element (one pixel-frame), counted from the update
 # equations on the executed branch with the i.i.d. input's mix (A-match 40 %,
@@ -188,18 +193,20 @@ def timed_launches(call, n, steps, warmup, stream):
     return ms, sum(durs) / len(durs)
 
 
-def roof(alg_bytes, k_ms, elems=None, ops=None):
+def roof(alg_bytes, k_ms, elems=None, ops=None, fp32=False):
     """HBM roofline of one launch (algorithmic bytes over its duration); with
-    the launch's elements and the algorithmic VALU ops per element, also both
-    ceilings in elements/s, the binding one and the fraction of it."""
+    the launch's elements and the algorithmic VALU ops per element (in FP32 or
+    FP64 arithmetic), also both ceilings in elements/s, the binding one and
+    the fraction of it."""
     gbs = alg_bytes / (k_ms * 1e-3) / 1e9
     out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4)}
     if elems and ops:
         rate = elems / (k_ms * 1e-3)
         hbm_c = HBM_PEAK_GBS * 1e9 * elems / alg_bytes
-        valu_c = VALU_PEAK_OPS / ops
+        valu_c = (VALU_PEAK_F32 if fp32 else VALU_PEAK_F64) / ops
         out["ceilings"] = {"bytes_per_element": round(alg_bytes / elems, 4), "ops_per_element": ops,
+                           "arithmetic": "f32" if fp32 else "f64",
                            "hbm_elements_per_s": round(hbm_c, 1),
                            "valu_elements_per_s": round(valu_c, 1),
                            "binding": "hbm" if hbm_c <= valu_c else "valu",
@@ -243,7 +250,7 @@ def leg_mixed(args, dsgm, sdev, torch):
     out = {
         "workload": "bf16 frames 1920x2560x500 seed 1, masks only",
         "fp32_state": {"elements_per_s": round(elems / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 4),
-                       "roofline": roof(elems * 3 + H * W * 36, float(sum(k32) / len(k32)), elems, OPS_STEP)},
+                       "roofline": roof(elems * 3 + H * W * 36, float(sum(k32) / len(k32)), elems, OPS_STEP, True)},
         "fp64_state": {"elements_per_s": round(elems / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 4),
                        "roofline": roof(elems * 3 + H * W * 68, float(sum(k64) / len(k64)), elems, OPS_STEP)},
         "speedup_fp32_over_fp64": round(ms64 / ms32, 3),
@@ -278,7 +285,7 @@ def leg_video(args, dsgm, sdev, torch):
         ms, kk = timed(lambda: dsgm.dsgm_forward(fr, st, p, masks), steps, 1, stream)
         out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
                      "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)),
-                                      elems, OPS_STEP)}
+                                      elems, OPS_STEP, acc_dt == torch.float32)}
         del fr, st, masks
         torch.cuda.empty_cache()
     return out
@@ -304,7 +311,7 @@ def leg_filtered(args, dsgm, sdev, torch):
         ms, kk = timed(lambda: dsgm.dsgm_forward_filtered(fr, st, p, filt, masks), steps, 1, stream)
         out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
                      "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)),
-                                      elems, OPS_PRE)}
+                                      elems, OPS_PRE, acc_dt == torch.float32)}
         del fr, st, masks
         torch.cuda.empty_cache()
     return out
@@ -477,10 +484,10 @@ def leg_adjoint(args, dsgm, sdev, torch):
     out = {
         "workload": "fp32 frames and state 1920x2560x500 seed 2, bg on, K=32",
         "forward": {"elements_per_s": round(elems / (msf * 1e-3), 1), "ms_per_step": round(msf, 4),
-                    "roofline": roof(fwd_bytes, float(sum(kf) / len(kf)), elems, OPS_STEP),
+                    "roofline": roof(fwd_bytes, float(sum(kf) / len(kf)), elems, OPS_STEP, True),
                     "checkpoint_bytes_written": ck_slots * px * 18},
         "backward": {"elements_per_s": round(elems / (msb * 1e-3), 1), "ms_per_step": round(msb, 4),
-                     "roofline": roof(bwd_bytes, float(sum(kb) / len(kb)), elems, OPS_ADJOINT),
+                     "roofline": roof(bwd_bytes, float(sum(kb) / len(kb)), elems, OPS_ADJOINT, True),
                      "checkpoint_bytes_read": ck_slots * px * 18},
         "grad_var_init": float(gvi.item()),
     }
@@ -651,7 +658,7 @@ def leg_batched(args, dsgm, sdev, torch):
            "autotuned_pixels_per_lane": tuned["vector"],
            "autotune_candidates_ms": {str(c["vector"]): round(c["ms"], 3) for c in tuned["candidates"]},
            "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-           "roofline": roof(alg, float(sum(kk) / len(kk)), elems, OPS_STEP),
+           "roofline": roof(alg, float(sum(kk) / len(kk)), elems, OPS_STEP, True),
            "fp64_form": {"workload": "the same 512 instances, fp64 frames (same values) and fp64 "
                                      "state, batched launches over %d chunks" % len(chunks),
                          "elements_per_s": round(elems / (ms64 * 1e-3), 1),

@@ -27,16 +27,20 @@ def test_roof_ceilings_hbm_binding():
     assert c["bytes_per_element"] == pytest.approx(9.0)
     assert c["hbm_elements_per_s"] == pytest.approx(8e12 / 9, rel=1e-9)
     assert c["valu_elements_per_s"] == pytest.approx(256 * 64 * 2.4e9 / 22, rel=1e-9)
-    assert c["binding"] == "hbm"
+    assert c["binding"] == "hbm" and c["arithmetic"] == "f64"
     assert c["frac_of_binding"] == pytest.approx(5e11 / (8e12 / 9), abs=1e-4)
 
 
 def test_roof_ceilings_valu_binding():
-    # 3 bytes and 22 ops per element: 2.67 T elt/s of HBM against 1.79 T of VALU
+    # 3 bytes and 22 FP64 ops per element: 2.67 T elt/s of HBM against 1.79 T of VALU
     r = bench.roof(3e9, 1.0, 1e9, 22)
     c = r["ceilings"]
     assert c["binding"] == "valu"
     assert c["frac_of_binding"] == pytest.approx(1e12 / (256 * 64 * 2.4e9 / 22), abs=1e-4)
+    # in FP32 the VALU ceiling doubles (3.57 T elt/s) and HBM binds
+    c = bench.roof(3e9, 1.0, 1e9, 22, fp32=True)["ceilings"]
+    assert c["arithmetic"] == "f32" and c["binding"] == "hbm"
+    assert c["valu_elements_per_s"] == pytest.approx(2 * 256 * 64 * 2.4e9 / 22, rel=1e-9)
 
 
 def test_source_hash_tracks_kernel_sources():
