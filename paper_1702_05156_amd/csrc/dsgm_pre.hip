@@ -155,6 +155,18 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
     }
   }
 
+  // this lane's outputs of the row and column passes (pairs of adjacent
+  // outputs, lane-strided) and the row pass's window start in the raw tile:
+  // the same every frame
+  constexpr int ROW_IT = (G::HB_N / 2 + NT - 1) / NT, COL_IT = (G::GB_N / 2 + NT - 1) / NT;
+  uint32_t row_src[ROW_IT];
+#pragma unroll
+  for (int it = 0; it < ROW_IT; ++it) {
+    const int pi = tid + it * NT;
+    const int r = pi / (G::HB_W / 2), v = 2 * (pi - r * (G::HB_W / 2));
+    row_src[it] = uint32_t(r * G::RAW_W + v);
+  }
+
   const In* frames = static_cast<const In*>(a.frames);
   In nxt[G::LOADS];
   auto load_frame = [&](int64_t t) {
@@ -180,35 +192,42 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
       // lane makes two horizontally adjacent outputs per step from one window
       // of 2*RG + 2 values (HB_W is even, so a pair never straddles rows)
       static_assert(G::HB_W % 2 == 0 && G::GB_W % 2 == 0, "output pairs stay in one row");
-      for (int pi = tid; pi < G::HB_N / 2; pi += NT) {
-        const int r = pi / (G::HB_W / 2), v = 2 * (pi - r * (G::HB_W / 2));
-        const Acc* src = buf_raw + r * G::RAW_W + v;
-        Acc win[2 * RG + 2];
 #pragma unroll
-        for (int j = 0; j < 2 * RG + 2; ++j) win[j] = src[j];
-        Acc a0 = Acc(0), a1 = Acc(0);
+      for (int it = 0; it < ROW_IT; ++it) {
+        const int pi = tid + it * NT;
+        if (it + 1 < ROW_IT || pi < G::HB_N / 2) {
+          const Acc* src = buf_raw + row_src[it];
+          Acc win[2 * RG + 2];
 #pragma unroll
-        for (int j = 0; j < 2 * RG + 1; ++j) {
-          a0 = tap(a0, wt[j], win[j]);
-          a1 = tap(a1, wt[j], win[j + 1]);
+          for (int j = 0; j < 2 * RG + 2; ++j) win[j] = src[j];
+          Acc a0 = Acc(0), a1 = Acc(0);
+#pragma unroll
+          for (int j = 0; j < 2 * RG + 1; ++j) {
+            a0 = tap(a0, wt[j], win[j]);
+            a1 = tap(a1, wt[j], win[j + 1]);
+          }
+          buf_hb[2 * pi] = a0;
+          buf_hb[2 * pi + 1] = a1;
         }
-        buf_hb[2 * pi] = a0;
-        buf_hb[2 * pi + 1] = a1;
       }
       __syncthreads();
       // 3. column pass: gb[r][v] = sum_i w_i hb[r + i][v], r in [0, GB_H); the
       // two tiles have the same width, so gb's row-major index is hb's
       static_assert(G::HB_W == G::GB_W, "row-blurred and blurred tiles share a width");
-      for (int pi = tid; pi < G::GB_N / 2; pi += NT) {
-        const Acc* src = buf_hb + 2 * pi;
-        Acc a0 = Acc(0), a1 = Acc(0);
 #pragma unroll
-        for (int j = 0; j < 2 * RG + 1; ++j) {
-          a0 = tap(a0, wt[j], src[j * G::HB_W]);
-          a1 = tap(a1, wt[j], src[j * G::HB_W + 1]);
+      for (int it = 0; it < COL_IT; ++it) {
+        const int pi = tid + it * NT;
+        if (it + 1 < COL_IT || pi < G::GB_N / 2) {
+          const Acc* src = buf_hb + 2 * pi;
+          Acc a0 = Acc(0), a1 = Acc(0);
+#pragma unroll
+          for (int j = 0; j < 2 * RG + 1; ++j) {
+            a0 = tap(a0, wt[j], src[j * G::HB_W]);
+            a1 = tap(a1, wt[j], src[j * G::HB_W + 1]);
+          }
+          buf_gb[2 * pi] = a0;
+          buf_gb[2 * pi + 1] = a1;
         }
-        buf_gb[2 * pi] = a0;
-        buf_gb[2 * pi + 1] = a1;
       }
       __syncthreads();
       gbp = buf_gb;
