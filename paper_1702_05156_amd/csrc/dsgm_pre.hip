@@ -83,7 +83,7 @@ __device__ __forceinline__ float tap<float>(float acc, float w, float x) {
   return __builtin_fmaf(w, x, acc);
 }
 
-template <typename In, typename Acc, typename Io, int RG, bool MED>
+template <typename In, typename Acc, typename Io, int RG, bool MED, bool PRINTED>
 __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
   using G = Geo<RG, MED>;
   constexpr int R = G::R, RM = G::RM;
@@ -98,7 +98,6 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
   fill_table<Acc>(tbl, a.weight_rule, a.age_max, a.var_init);  // ends with a barrier
   const StepConsts<Acc> k =
       make_consts<Acc>(a.theta_s, a.theta_d, a.var_init, a.var_floor, a.mask_floor);
-  const bool printed = a.mask_rule != 0;
 
   Acc wt[2 * RG + 1];
 #pragma unroll
@@ -278,7 +277,7 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
     Vec<Io, PX> fv;  // the filtered frame in the array type
 #pragma unroll
     for (int q = 0; q < PX; ++q) {
-      rec[q].fg = printed ? fg_of<Acc, true>(s[q], xs[q], k) : fg_of<Acc, false>(s[q], xs[q], k);
+      rec[q].fg = fg_of<Acc, PRINTED>(s[q], xs[q], k);
       mk.v[q] = rec[q].fg ? uint8_t(255) : uint8_t(0);
       cd.v[q] = uint8_t(code_of<Acc>(rec[q]));
       bgv.v[q] = Io(s[q].mA);
@@ -315,15 +314,15 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
   }
 }
 
-template <typename In, typename Acc, typename Io, bool MED>
+template <typename In, typename Acc, typename Io, bool MED, bool PRINTED>
 hipError_t launch_rg(const PreArgs& a, int rg, hipStream_t stream) {
   const int64_t nb = a.tiles_x * a.tiles_y;
   const dim3 grid{uint32_t(nb), 1, 1}, block{NT, 1, 1};
   switch (rg) {
-    case 0: hipLaunchKernelGGL((pre_kernel<In, Acc, Io, 0, MED>), grid, block, 0, stream, a); break;
-    case 1: hipLaunchKernelGGL((pre_kernel<In, Acc, Io, 1, MED>), grid, block, 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((pre_kernel<In, Acc, Io, 2, MED>), grid, block, 0, stream, a); break;
-    case 3: hipLaunchKernelGGL((pre_kernel<In, Acc, Io, 3, MED>), grid, block, 0, stream, a); break;
+    case 0: hipLaunchKernelGGL((pre_kernel<In, Acc, Io, 0, MED, PRINTED>), grid, block, 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((pre_kernel<In, Acc, Io, 1, MED, PRINTED>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((pre_kernel<In, Acc, Io, 2, MED, PRINTED>), grid, block, 0, stream, a); break;
+    case 3: hipLaunchKernelGGL((pre_kernel<In, Acc, Io, 3, MED, PRINTED>), grid, block, 0, stream, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -331,8 +330,12 @@ hipError_t launch_rg(const PreArgs& a, int rg, hipStream_t stream) {
 
 template <typename In, typename Acc, typename Io>
 hipError_t launch_t(const PreArgs& a, int rg, bool median, hipStream_t stream) {
-  return median ? launch_rg<In, Acc, Io, true>(a, rg, stream)
-                : launch_rg<In, Acc, Io, false>(a, rg, stream);
+  const bool printed = a.mask_rule != 0;
+  if (median)
+    return printed ? launch_rg<In, Acc, Io, true, true>(a, rg, stream)
+                   : launch_rg<In, Acc, Io, true, false>(a, rg, stream);
+  return printed ? launch_rg<In, Acc, Io, false, true>(a, rg, stream)
+                 : launch_rg<In, Acc, Io, false, false>(a, rg, stream);
 }
 
 }  // namespace pre
