@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -110,8 +111,10 @@ int check_shape(const dsgm_shape& s, size_t max_elem_bytes) {
   return DSGM_OK;
 }
 
-int g_block_override = 0;  // set by dsgm_set_launch (tuning)
-int g_vector_override = 0;
+// set by dsgm_set_launch (tuning) while other threads may be launching:
+// atomics, read once per call
+std::atomic<int> g_block_override{0};
+std::atomic<int> g_vector_override{0};
 
 // Launch shapes chosen by dsgm_autotune, per (frame type, state type, H, W,
 // output flags); dsgm_forward looks its arguments up here.
@@ -204,7 +207,8 @@ int plan_layout(const dsgm_instance* inst, int32_t n, int in_dtype, int acc, Pla
   }
   const int widest = P;
   P = std::min(P, preferred_vector(in_dtype, acc));
-  if (g_vector_override && widest % g_vector_override == 0) P = g_vector_override;
+  const int vo = g_vector_override.load(std::memory_order_relaxed);
+  if (vo && widest % vo == 0) P = vo;
   int64_t items = 0, total = 0;
   for (int32_t i = 0; i < n; ++i) {
     const dsgm_shape& s = inst[i].shape;
@@ -361,12 +365,13 @@ int forward_impl(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   const int tflags = (bg ? DSGM_TUNE_BG : 0) | (ckpt ? DSGM_TUNE_CKPT : 0) |
                      (params->mask_rule == DSGM_MASK_PRINTED ? DSGM_TUNE_PRINTED : 0);
   int tb = force_block, tv = force_vector;
-  if (!tb && !g_block_override && !g_vector_override)
-    tune_lookup(TuneKey{in_dtype, acc, shape.H, shape.W, tflags}, &tb, &tv);
+  const int bo = g_block_override.load(std::memory_order_relaxed);
+  const int vo = g_vector_override.load(std::memory_order_relaxed);
+  if (!tb && !bo && !vo) tune_lookup(TuneKey{in_dtype, acc, shape.H, shape.W, tflags}, &tb, &tv);
   if (tb) block = tb;
   if (tv && legal(tv)) P = tv;
-  if (g_vector_override && legal(g_vector_override)) P = g_vector_override;
-  if (g_block_override) block = g_block_override;
+  if (vo && legal(vo)) P = vo;
+  if (bo) block = bo;
   if (codes && !as_run) P = 1;  // the decision-code (debug) variants run one pixel per lane
 
   dsgm::FwdArgs a;
@@ -1023,8 +1028,8 @@ int dsgm_set_launch(int32_t block, int32_t vector) {
     return fail(DSGM_E_ARG, "block = %d: must be 0 or a multiple of 64 in 64..256", block);
   if (vector != 0 && vector != 1 && vector != 2 && vector != 4)
     return fail(DSGM_E_ARG, "vector = %d: must be 0, 1, 2 or 4", vector);
-  g_block_override = block;
-  g_vector_override = vector;
+  g_block_override.store(block, std::memory_order_relaxed);
+  g_vector_override.store(vector, std::memory_order_relaxed);
   return ok();
 }
 

@@ -319,3 +319,33 @@ def test_autotune_arguments_rejected_before_any_hip_call():
     assert lib.dsgm_autotune_lookup(dsgm.IN_F64, dsgm.ACC_F64, S(5, 8, 8), 0, None) == -1
     with pytest.raises(dsgm.DSGMError):
         dsgm.dsgm_autotune_lookup(dsgm.IN_F64, dsgm.ACC_F64, 5, 8, 8, 16)
+
+
+def test_host_tables_are_thread_safe():
+    """The process-wide launch override and the tuner's table are shared by all
+    threads: concurrent setters, lookups and clears from many threads (ctypes
+    drops the GIL around each call) leave them consistent."""
+    import threading
+    S = dsgm._tune_shape
+    errors = []
+
+    def worker(k):
+        try:
+            chosen = (ctypes.c_int32 * 2)()
+            for i in range(2000):
+                assert lib.dsgm_set_launch(64 * (1 + (i + k) % 4), (1, 2, 4)[(i * k) % 3]) == 0
+                assert lib.dsgm_autotune_lookup(dsgm.IN_F32, dsgm.ACC_F32, S(4, 8, 8 + k), 0,
+                                                chosen) == 0
+                assert list(chosen) == [0, 0]
+                if i % 97 == 0:
+                    assert lib.dsgm_autotune_clear() == 0
+        except AssertionError as e:  # pragma: no cover - reported below
+            errors.append((k, e))
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors
+    assert lib.dsgm_set_launch(0, 0) == 0
