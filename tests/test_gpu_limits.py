@@ -1,0 +1,62 @@
+"""Parity at the size limits of the ABI.
+
+A frame may span up to 2^31 bytes (the kernels address a frame with a 32-bit
+per-lane offset on top of a per-frame base), and H*W must stay below 2^31.
+These tests run the forward and the adjoint on FP64 frames just under that
+limit, bg and checkpoints on, and compare sampled pixels -- the first and last
+pixel of the frame among them, where the offsets are largest -- with the
+oracle.  Pixels are independent, so a sample is an exact check of those
+pixels.  The ABI's rejection of larger frames is tested on the CPU
+(test_abi.py).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import device as sdev
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+
+# 8192 x 32766 FP64 pixels: 2,147,352,576 bytes per frame, 131,072 under 2^31
+H, W = 8192, 32766
+
+
+@pytest.mark.slow
+def test_forward_and_adjoint_at_the_frame_size_limit():
+    T, K, seed = 3, 2, 71
+    assert H * W * 8 < 2 ** 31 and (H * W + 16384) * 8 >= 2 ** 31
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(seed, T, H, W)
+    out = dsgm.forward(fr, st, p, bg=True, ckpt_every=K)
+    gbg = sdev.grad_bg(seed + 100, T, H, W, torch.float64)
+    gst = tuple(g.contiguous() for g in sdev.grad_state(seed + 100, H, W, torch.float64))
+    r = dsgm.backward(fr, p, out["ckpt"], K, dsgm.ACC_F64, gbg, gst)
+    torch.cuda.synchronize()
+
+    rng = np.random.default_rng(71)
+    n = H * W
+    pix = np.unique(np.concatenate([rng.choice(n, 2048, replace=False),
+                                    [0, 1, W - 1, W, n - W - 1, n - W, n - 2, n - 1]]))
+    pt = torch.as_tensor(pix, device="cuda")
+    x, st0 = G.host_case(seed, T, H, W, pix=pix)
+    ref = oracle.forward(x, st0, G.oracle_params(p), bg=True, codes=True)
+    G.assert_bit_exact("masks", out["masks"].view(T, -1)[:, pt].cpu().numpy(), ref["masks"])
+    G.assert_bit_exact("bg", out["bg"].view(T, -1)[:, pt].cpu().numpy(), ref["bg"])
+    for k, plane in zip(("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"), st.planes()):
+        got = plane.view(-1)[pt].cpu().numpy()
+        G.assert_bit_exact(k, got.astype(np.int32) if k.startswith("age") else got, ref[k])
+
+    gb = gbg.view(T, -1)[:, pt].cpu().numpy()
+    gs = np.stack([g.view(-1)[pt].cpu().numpy() for g in gst])
+    rb = oracle.backward(x, st0, G.oracle_params(p), gb, gs, forced=ref["codes"].astype(np.uint8))
+    G.assert_bit_exact("grad_frames", r["grad_frames"].view(T, -1)[:, pt].cpu().numpy(),
+                       rb["grad_frames"])
+    for i in range(4):
+        G.assert_bit_exact(f"grad_state0[{i}]", r["grad_state0"][i].view(-1)[pt].cpu().numpy(),
+                           rb["grad_state0"][i])
+    # a property that holds at any size: masks are 0/255 everywhere
+    assert int(((out["masks"] != 0) & (out["masks"] != 255)).sum()) == 0
