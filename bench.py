@@ -257,6 +257,32 @@ def roof(alg_bytes, k_ms, elems=None, ops=None, fp32=False):
     return out
 
 
+def fp64_error(dsgm, torch, run, fr, st_lo, var_init):
+    """Error of one reduced-precision pass against the FP64 pass on the same
+    frames from the same start (the FP64 state holds the reduced state's
+    values, so both see identical inputs; the FP64 GPU path is the oracle's
+    arithmetic bit for bit).  run(state, masks, codes) makes one pass.  A pixel
+    has diverged once any of its decisions differs."""
+    T, H, W = fr.shape
+    a_lo = dsgm.State(*(t.clone() for t in st_lo.planes()))
+    a64 = dsgm.State(st_lo.mean_a.double(), st_lo.var_a.double(), st_lo.mean_c.double(),
+                     st_lo.var_c.double(), st_lo.age_a.clone(), st_lo.age_c.clone())
+    m_lo = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    m64, c_lo, c64 = torch.empty_like(m_lo), torch.empty_like(m_lo), torch.empty_like(m_lo)
+    run(a_lo, m_lo, c_lo)
+    run(a64, m64, c64)
+    torch.cuda.synchronize()
+    div = ((c_lo & 15) != (c64 & 15)).any(dim=0)
+    same = ~div
+    dm = (a_lo.mean_a.double() - a64.mean_a).abs()
+    dv = (a_lo.var_a.double() - a64.var_a).abs() / torch.clamp(a64.var_a, min=var_init)
+    out = {"mask_elements_differing_frac": float((m_lo != m64).sum().item()) / (T * H * W),
+           "pixels_with_any_decision_difference_frac": float(div.sum().item()) / (H * W),
+           "max_abs_mean_a_err_undiverged": float(dm[same].max().item()) if bool(same.any()) else None,
+           "max_rel_var_a_err_undiverged": float(dv[same].max().item()) if bool(same.any()) else None}
+    return out, same
+
+
 # ---------------------------------------------------------------- legs
 def leg_mixed(args, dsgm, sdev, torch):
     """BF16 frames: FP32 state vs FP64 state on the same frames."""
@@ -325,10 +351,15 @@ def leg_video(args, dsgm, sdev, torch):
         st = dsgm.State.empty(H, W, acc_dt)
         dsgm.dsgm_state_init_from_frame(fr[0], st, p)
         masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+        st0 = dsgm.State(*(t.clone() for t in st.planes()))
         ms, kk = timed(lambda: dsgm.dsgm_forward(fr, st, p, masks), steps, 1, stream)
         out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
                      "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)),
                                       elems, OPS_STEP, acc_dt == torch.float32)}
+        if acc_dt == torch.float32:
+            out[name]["error_vs_fp64"], _ = fp64_error(
+                dsgm, torch, lambda s_, m_, c_: dsgm.dsgm_forward(fr, s_, p, m_, codes=c_), fr, st0,
+                p.var_init)
         del fr, st, masks
         torch.cuda.empty_cache()
     return out
@@ -351,11 +382,19 @@ def leg_filtered(args, dsgm, sdev, torch):
         fr = sdev.frames(seed, T, H, W, in_dt)
         st = dsgm.State(*sdev.state(seed, H, W, acc_dt))
         masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+        st0 = dsgm.State(*(t.clone() for t in st.planes()))
         ms, kk = timed(lambda: dsgm.dsgm_forward_filtered(fr, st, p, filt, masks), steps, 1, stream)
+        if acc_dt == torch.float32:
+            err, _ = fp64_error(
+                dsgm, torch,
+                lambda s_, m_, c_: dsgm.dsgm_forward_filtered(fr, s_, p, filt, m_, codes=c_),
+                fr, st0, p.var_init)
         out[name] = {"elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
                      "roofline": roof(elems * (in_b + 1) + px * st_b, float(sum(kk) / len(kk)),
                                       elems, OPS_PRE, acc_dt == torch.float32)}
-        del fr, st, masks
+        if acc_dt == torch.float32:
+            out[name]["error_vs_fp64"] = err
+        del fr, st, st0, masks
         torch.cuda.empty_cache()
     return out
 
@@ -520,6 +559,28 @@ def leg_adjoint(args, dsgm, sdev, torch):
     dsgm.dsgm_forward(fr, st, p, masks, bg, ck, K)
     msb, kb = timed(lambda: dsgm.dsgm_backward(fr, p, ck, K, dsgm.ACC_F32, gbg, gst, gx, gs0, gvi, ws),
                     steps, 1, stream)
+    # error against the FP64 forward and adjoint on the same inputs (upstream
+    # gradients upcast); gradients compared on the pixels whose decisions agree
+    ferr, same = fp64_error(dsgm, torch, lambda s_, m_, c_: dsgm.dsgm_forward(fr, s_, p, m_, codes=c_),
+                            fr, st0, p.var_init)
+    s64 = dsgm.State(st0.mean_a.double(), st0.var_a.double(), st0.mean_c.double(),
+                     st0.var_c.double(), st0.age_a.clone(), st0.age_c.clone())
+    r64 = dsgm.backward(fr, p, dsgm.forward(fr, s64, p, ckpt_every=K)["ckpt"], K, dsgm.ACC_F64,
+                        gbg.double(), tuple(g.double() for g in gst))
+    torch.cuda.synchronize()
+    keep = same.view(1, -1).double()  # 1 on undiverged pixels
+    num = den = 0.0
+    for t0 in range(0, T, 50):  # in frame chunks: no full-size FP64 temporaries
+        g32 = gx[t0:t0 + 50].reshape(-1, H * W).double()
+        g64 = r64["grad_frames"][t0:t0 + 50].reshape(-1, H * W)
+        num += float((((g32 - g64) * keep) ** 2).sum())
+        den += float(((g64 * keep) ** 2).sum())
+    snum = sum(float((((a.reshape(1, -1).double() - b.reshape(1, -1)) * keep) ** 2).sum())
+               for a, b in zip(gs0, r64["grad_state0"]))
+    sden = sum(float(((b.reshape(1, -1) * keep) ** 2).sum()) for b in r64["grad_state0"])
+    berr = {"grad_frames_rel_l2_undiverged": (num / den) ** 0.5,
+            "grad_state0_rel_l2_undiverged": (snum / sden) ** 0.5}
+    del s64, r64, g32, g64, same, keep
     elems, px = T * H * W, H * W
     ck_slots = (T + K - 1) // K
     fwd_bytes = elems * (4 + 1 + 4) + px * 36
@@ -533,6 +594,7 @@ def leg_adjoint(args, dsgm, sdev, torch):
                      "roofline": roof(bwd_bytes, float(sum(kb) / len(kb)), elems, OPS_ADJOINT, True),
                      "checkpoint_bytes_read": ck_slots * px * 18},
         "grad_var_init": float(gvi.item()),
+        "error_vs_fp64": dict(ferr, **berr),
     }
     del fr, st, st0, masks, bg, ck, gbg, gst, gx, gs0, gvi, ws
     torch.cuda.empty_cache()
