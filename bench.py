@@ -632,6 +632,25 @@ def leg_largest(args, dsgm, sdev, torch):
     dsgm.dsgm_forward(fr, st, p, masks, bg, ck, K, acc=acc)
     msb, kb = timed(lambda: dsgm.dsgm_backward(fr, p, ck, K, acc, gbg, gst, gx, gs0, gvi, ws),
                     steps, 1, stream)
+    # error against FP64 arrays on a band of rows (pixels are independent, so
+    # the band run alone is the full run's arithmetic for those pixels): the
+    # FP32 bg and gradients must be the FP64 values rounded once
+    R = 64
+    sb = dsgm.State(*(t[:R].contiguous() for t in st0.planes()))
+    fb = fr[:, :R].contiguous()  # dense, so the outputs dsgm.forward allocates are too
+    ob = dsgm.forward(fb, sb, p, bg=True, ckpt_every=K)
+    rb = dsgm.backward(fb, p, ob["ckpt"], K, dsgm.ACC_F64, gbg[:, :R].double(),
+                       tuple(g[:R].double() for g in gst))
+    torch.cuda.synchronize()
+    bg64, gx64 = ob["bg"], rb["grad_frames"]
+    rel = lambda a, b: float(((a.double() - b).abs() / b.abs().clamp(min=1e-300)).max())
+    err = {"band": f"rows 0-{R - 1}, all {T} frames",
+           "masks_equal": bool(torch.equal(masks[:, :R], ob["masks"])),
+           "bg_equals_fp64_rounded_once": bool(torch.equal(bg[:, :R], bg64.float())),
+           "grad_frames_equal_fp64_rounded_once": bool(torch.equal(gx[:, :R], gx64.float())),
+           "max_rel_err_bg": rel(bg[:, :R], bg64),
+           "max_rel_err_grad_frames": rel(gx[:, :R], gx64)}
+    del sb, fb, ob, rb, bg64, gx64
     elems, px = T * H * W, H * W
     ck_slots = (T + K - 1) // K
     out = {"workload": "2160x3840x1344 fp32 frames, fp64 state, fp32 bg/gradients, K=32, seed 4",
@@ -642,7 +661,8 @@ def leg_largest(args, dsgm, sdev, torch):
            "backward": {"elements_per_s": round(elems / (msb * 1e-3), 1), "ms_per_step": round(msb, 3),
                         "roofline": roof(elems * 12 + px * 40, float(sum(kb) / len(kb)), elems, OPS_ADJOINT),
                         "checkpoint_bytes_read": ck_slots * px * 34},
-           "grad_var_init": float(gvi.item())}
+           "grad_var_init": float(gvi.item()),
+           "error_vs_fp64": err}
     del fr, st, st0, masks, bg, ck, gbg, gst, gx, gs0, gvi, ws
     torch.cuda.empty_cache()
     return out
