@@ -18,8 +18,8 @@ dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
 
 
 
-def _case(seed, T, H, W, n, median, in_dtype=torch.float64, sigma=1.0, frames=None):
-    p = dsgm.dsgm_params_default(2.0)
+def _case(seed, T, H, W, n, median, in_dtype=torch.float64, sigma=1.0, frames=None, params=None):
+    p = params or dsgm.dsgm_params_default(2.0)
     filt = dsgm.gauss_filter(n, sigma, median) if n else dsgm.gauss_filter(0, 1.0, median)
     fr, st = G.device_case(seed, T, H, W, in_dtype, torch.float64)
     if frames is not None:
@@ -41,6 +41,23 @@ def test_filtered_frames_and_update_f64_bit_exact(n, median):
     G.assert_bit_exact("codes", G.flat(out["codes"]), ref["codes"])
     G.assert_bit_exact("masks", G.flat(out["masks"]), ref["masks"])
     G.assert_bit_exact("bg", G.flat(out["bg"]), ref["bg"])
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k], ref[k])
+
+
+@pytest.mark.parametrize("wr,mr", [(1, 0), (0, 1), (1, 1)])
+def test_filtered_other_rules_f64_bit_exact(wr, mr):
+    """The appendix's weights (1/a) and its printed mask rule on the fused path
+    (the mask rule selects a compiled variant of the kernel)."""
+    p = dsgm.dsgm_params_default(2.0, mr)
+    p.weight_rule = wr
+    T, H, W = 15, 37, 150
+    p, out, st, xf, st0 = _case(42, T, H, W, 5, 1, params=p)
+    G.assert_bit_exact("filtered", G.flat(out["filtered"]), xf)
+    ref = oracle.forward(xf, st0, G.oracle_params(p))
+    G.assert_bit_exact("codes", G.flat(out["codes"]), ref["codes"])
+    G.assert_bit_exact("masks", G.flat(out["masks"]), ref["masks"])
     hs = G.state_to_host(st)
     for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
         G.assert_bit_exact(k, hs[k], ref[k])

@@ -15,8 +15,9 @@ pytestmark = pytest.mark.gpu
 dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
 
 
-def _run(seed, T, H, W, b, in_dtype=torch.float64, acc_dtype=torch.float64, frames=None):
-    p = dsgm.dsgm_params_default(2.0)
+def _run(seed, T, H, W, b, in_dtype=torch.float64, acc_dtype=torch.float64, frames=None,
+         params=None):
+    p = params or dsgm.dsgm_params_default(2.0)
     Hb, Wb = -(-H // b), -(-W // b)
     fr = sdev.frames(seed, T, H, W, in_dtype)
     if frames is not None:
@@ -44,6 +45,23 @@ def test_grid_f64_bit_exact(b, T, H, W):
         G.assert_bit_exact(k, hs[k], ref[k])
     # bg: the block's mean_A after each frame, in the oracle the running mean_a
     assert np.array_equal(bg[-1].cpu().numpy().ravel(), ref["mean_a"])
+
+
+@pytest.mark.parametrize("b", [1, 4])
+@pytest.mark.parametrize("wr,mr", [(1, 0), (0, 1), (1, 1)])
+def test_grid_other_rules_f64_bit_exact(b, wr, mr):
+    """The appendix's weights and its printed mask rule (against each pixel's
+    own intensity) on the grid model."""
+    p = dsgm.dsgm_params_default(2.0, mr)
+    p.weight_rule = wr
+    T, H, W = 30, 21, 46
+    p, st, masks, bg, codes, x, st0 = _run(63, T, H, W, b, params=p)
+    ref = oracle.forward_grid(x, st0, G.oracle_params(p), b)
+    G.assert_bit_exact("codes", codes.cpu().numpy().reshape(T, -1), ref["codes"])
+    G.assert_bit_exact("masks", masks.cpu().numpy(), ref["masks"])
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k], ref[k])
 
 
 def test_grid_strided_frames_scalar_path():

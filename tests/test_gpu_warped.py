@@ -61,6 +61,29 @@ def test_warped_step_f64_bit_exact(name, H, W):
         G.assert_bit_exact("src " + k, hs0[k], np.asarray(st0[k]).astype(hs0[k].dtype))
 
 
+@pytest.mark.parametrize("wr,mr", [(1, 0), (0, 1), (1, 1)])
+def test_warped_other_rules_f64_bit_exact(wr, mr):
+    """The appendix's weights and its printed mask rule on the motion-compensated
+    step."""
+    H, W = 37, 61
+    p = dsgm.dsgm_params_default(2.0, mr)
+    p.weight_rule = wr
+    m = _maps(H, W)["rigid"]
+    fr, src = G.device_case(54, 1, H, W)
+    dst = dsgm.State.empty(H, W)
+    masks = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    codes = torch.empty_like(masks)
+    dsgm.dsgm_forward_warped(fr[0], src, dst, p, m, masks, None, codes)
+    torch.cuda.synchronize()
+    x, st0 = G.host_case(54, 1, H, W)
+    ref = _oracle_step(st0, x[0], m, p, H, W)
+    G.assert_bit_exact("codes", codes.cpu().numpy().reshape(1, -1), ref["codes"])
+    G.assert_bit_exact("masks", masks.cpu().numpy().reshape(1, -1), ref["masks"])
+    hs = G.state_to_host(dst)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k], ref[k])
+
+
 def test_warped_stream_of_frames_f64():
     """A panning camera over the structured video: 30 frames, each with its own
     small homography, ping-ponging two state buffers, against the oracle loop."""
