@@ -60,6 +60,23 @@ def test_f64_adjoint_bit_exact(K):
     assert gvi == pytest.approx(ref["grad_var_init"], rel=1e-15, abs=1e-300)
 
 
+@pytest.mark.parametrize("in_dtype", [torch.float64, torch.float32])
+def test_f64_adjoint_appendix_weights_bit_exact(in_dtype):
+    """The adjoint under the appendix's weights (w = 1/a), FP64 arithmetic,
+    against the oracle's reverse mode under the same decisions."""
+    T, H, W, K, seed = 60, 10, 24, 16, 28
+    p = dsgm.dsgm_params_default(2.0, dsgm.MASK_PRINTED)
+    p.weight_rule = dsgm.WEIGHT_APPENDIX
+    p_, out, r, gbg, gst = _gpu_fwd_bwd(seed, T, H, W, K, in_dtype, torch.float64, params=p)
+    ref = _oracle_bwd(seed, T, H, W, in_dtype, torch.float64, p, out["codes"], gbg, gst)
+    G.assert_bit_exact("grad_frames", G.flat(r["grad_frames"]), ref["grad_frames"])
+    for i, name in enumerate(("mean_a", "var_a", "mean_c", "var_c")):
+        G.assert_bit_exact(f"grad_{name}0", r["grad_state0"][i].cpu().numpy().ravel(),
+                           ref["grad_state0"][i])
+    px = r["workspace"][: H * W * 8].view(torch.float64).cpu().numpy()
+    G.assert_bit_exact("grad_var_init per pixel", px, ref["grad_var_init_px"])
+
+
 def test_adjoint_does_not_depend_on_checkpoint_interval():
     T, H, W, seed = 70, 8, 64, 22
     res = [_gpu_fwd_bwd(seed, T, H, W, K, torch.float32, torch.float32)[2] for K in (1, 5, 32, 33, 70)]

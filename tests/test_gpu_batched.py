@@ -77,6 +77,27 @@ def test_batched_ragged_widths_and_oracle():
             G.assert_bit_exact(f"{k}[{i}]", hs[k], ref[k])
 
 
+@pytest.mark.parametrize("wr,mr", [(1, 1), (0, 1), (1, 0)])
+def test_batched_other_rules_f64_oracle(wr, mr):
+    """The appendix's weights and its printed mask rule (a compiled variant of
+    the persistent kernel) on a batch, FP64, every instance against the oracle."""
+    shapes = [(25, 6, 16), (40, 9, 32), (3, 4, 8)]
+    p = dsgm.dsgm_params_default(2.0, mr)
+    p.weight_rule = wr
+    items, _ = _make(shapes, torch.float64, torch.float64, seed0=450)
+    batch = dsgm.Batch(items)
+    batch.run(p)
+    torch.cuda.synchronize()
+    for i, ((fr, st, masks, bg), (T, H, W)) in enumerate(zip(items, shapes)):
+        x, s0 = G.host_case(450 + i, T, H, W)
+        ref = oracle.forward(x, s0, G.oracle_params(p))
+        G.assert_bit_exact(f"masks[{i}]", G.flat(masks), ref["masks"])
+        G.assert_bit_exact(f"bg[{i}]", G.flat(bg), ref["bg"])
+        hs = G.state_to_host(st)
+        for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+            G.assert_bit_exact(f"{k}[{i}]", hs[k], ref[k])
+
+
 def test_batched_lpt_order_and_plan():
     p = dsgm.dsgm_params_default(2.0)
     items, _ = _make(SHAPES, torch.float32, torch.float32)
