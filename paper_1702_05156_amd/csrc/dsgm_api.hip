@@ -511,7 +511,7 @@ int dsgm_autotune(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape, int32_
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "dsgm_autotune event");
   if ((e = hipEventCreate(&e1)) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return hip_fail(e, "dsgm_autotune event");
   }
   // two rounds over the candidates, each candidate's time the better of its
@@ -552,8 +552,8 @@ int dsgm_autotune(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape, int32_
     if (best_ms[c] >= 0.f && (best < 0 || best_ms[c] < best_ms[best])) best = c;
   const int best_block = best >= 0 ? blocks[best / 3] : 256;
   const int best_vector = best >= 0 ? vectors[best % 3] : 1;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);  // release failures change nothing for the caller
+  (void)hipEventDestroy(e1);
   if (rc != DSGM_OK) return rc;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
