@@ -69,6 +69,29 @@ def test_u8_streaming_equals_fused_and_no_codes_path():
         assert torch.equal(u, v)
 
 
+@pytest.mark.parametrize("wr,mr", [(1, 1), (0, 0)])
+@pytest.mark.parametrize("H,W", [(16, 128), (9, 30), (5, 37), (1, 1)])
+def test_u8_one_frame_steps_against_the_oracle(wr, mr, H, W):
+    """One call per frame (the persistent one-frame kernel; widths of 4, 2 and
+    1 pixel per lane) with codes: every frame's masks and codes and the final
+    stored state equal the 8-bit oracle's."""
+    T = 12
+    x, st = _case(76, T, H, W)
+    p = _params(wr, mr)
+    fr = torch.as_tensor(x, device="cuda")
+    s = _dev_state(st, H, W)
+    m = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    c = torch.empty_like(m)
+    for t in range(T):
+        dsgm.dsgm_forward(fr[t:t + 1], s, p, m[t:t + 1], codes=c[t:t + 1])
+    torch.cuda.synchronize()
+    ref = oracle.forward_u8(x.reshape(T, -1), st, G.oracle_params(p))
+    G.assert_bit_exact("masks", m.cpu().numpy().reshape(T, -1), ref["masks"])
+    G.assert_bit_exact("codes", c.cpu().numpy().reshape(T, -1), ref["codes"])
+    for k, plane in zip(("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"), s.planes()):
+        G.assert_bit_exact(k, plane.cpu().numpy().ravel().astype(ref[k].dtype), ref[k])
+
+
 def test_u8_init_from_frame_and_rejections():
     H, W = 5, 9
     p = _params(1, 1)
