@@ -119,6 +119,7 @@ def cpu_baseline(T, H, W, seed, target_s=10.0, chunk_rows=32):
     import synth
 
     p = oracle.default_params(2.0)
+    cores = oracle.max_threads()  # read first: a thread count passed to the oracle sticks
     done_rows, n, dt = 0, 0, 0.0
     while done_rows < H and dt < target_s:
         rows = min(chunk_rows, H - done_rows)
@@ -126,7 +127,7 @@ def cpu_baseline(T, H, W, seed, target_s=10.0, chunk_rows=32):
         x = synth.frames(seed, T, H, W, "f64", pix=pix)
         st = synth.state(seed, H, W, "f64", 30, pix=pix)
         t0 = time.perf_counter()
-        oracle.forward(x, st, p, bg=False, codes=False)
+        oracle.forward(x, st, p, bg=False, codes=False, nthreads=cores)
         dt += time.perf_counter() - t0
         n += rows * W * T
         done_rows += rows
@@ -140,7 +141,7 @@ def cpu_baseline(T, H, W, seed, target_s=10.0, chunk_rows=32):
     oracle.forward(x, st, p, bg=False, codes=False, nthreads=1)
     dt1 = time.perf_counter() - t0
     n1 = rows * W * T
-    return {"value": n / dt, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
+    return {"value": n / dt, "unit": "elements/s", "cores": cores, "kind": "oracle",
             "sample": f"rows 0-{done_rows - 1} of {H} x {W} columns x {T} frames = {n} elements "
                       f"(FP64 scalar C, OpenMP over pixel chunks), {dt:.2f} s of oracle time",
             "cpu_model": cpu_model(),
