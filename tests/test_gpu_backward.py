@@ -318,3 +318,47 @@ def test_full_size_io32_forward_and_adjoint_sampled():
         G.assert_bit_exact(f"grad_state0[{i}]", r["grad_state0"][i].view(-1)[pt].cpu().numpy(),
                            rb["grad_state0"][i].astype(np.float32))
     del fr, st, st0, masks, bg, ck, gbg, gst, r
+
+
+@pytest.mark.parametrize("in_dtype,acc_dtype", [(torch.float64, torch.float64),
+                                                (torch.bfloat16, torch.float32)])
+def test_run_to_run_determinism(in_dtype, acc_dtype):
+    """Two runs of the forward and the adjoint on the same inputs give the same
+    bits, the two-pass reduction of d/d var_init included (no atomics anywhere
+    in a floating-point result)."""
+    T, H, W, K, seed = 90, 33, 200, 16, 29
+    runs = [_gpu_fwd_bwd(seed, T, H, W, K, in_dtype, acc_dtype) for _ in range(2)]
+    (_, o1, r1, _, _), (_, o2, r2, _, _) = runs
+    for k in ("masks", "bg", "codes", "ckpt"):
+        assert torch.equal(o1[k], o2[k]), k
+    assert torch.equal(r1["grad_frames"], r2["grad_frames"])
+    for a, b in zip(r1["grad_state0"], r2["grad_state0"]):
+        assert torch.equal(a, b)
+    assert r1["grad_var_init"].cpu().numpy().tobytes() == r2["grad_var_init"].cpu().numpy().tobytes()
+
+
+def test_pixel_permutation_equivariance():
+    """Pixels are independent: mirroring the frames and the state left-right
+    mirrors every per-pixel output and gradient, and leaves d/d var_init equal
+    up to the summation order of its reduction."""
+    T, H, W, K, seed = 50, 20, 72, 16, 30
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(seed, T, H, W)
+    gbg, gst = _grads(seed + 100, T, H, W, torch.float64)
+    flip = lambda t: t.flip(-1).contiguous()
+    st_f = dsgm.State(*(flip(t) for t in st.planes()))
+    out = dsgm.forward(fr, st, p, bg=True, codes=True, ckpt_every=K)
+    out_f = dsgm.forward(flip(fr), st_f, p, bg=True, codes=True, ckpt_every=K)
+    r = dsgm.backward(fr, p, out["ckpt"], K, dsgm.ACC_F64, gbg, gst)
+    r_f = dsgm.backward(flip(fr), p, out_f["ckpt"], K, dsgm.ACC_F64, flip(gbg),
+                        tuple(flip(g) for g in gst))
+    torch.cuda.synchronize()
+    for k in ("masks", "bg", "codes"):
+        assert torch.equal(flip(out[k]), out_f[k]), k
+    for a, b in zip(st.planes(), st_f.planes()):
+        assert torch.equal(flip(a), b)
+    assert torch.equal(flip(r["grad_frames"]), r_f["grad_frames"])
+    for a, b in zip(r["grad_state0"], r_f["grad_state0"]):
+        assert torch.equal(flip(a), b)
+    assert float(r["grad_var_init"].item()) == pytest.approx(float(r_f["grad_var_init"].item()),
+                                                            rel=1e-13)
