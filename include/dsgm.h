@@ -33,7 +33,8 @@
  *   - Calls are reentrant; concurrent calls on different streams that touch
  *     disjoint memory are independent.
  *   - NaN or infinite intensities are not supported: results are whatever the
- *     IEEE comparisons make of them (memory safety is unaffected).
+ *     IEEE comparisons make of them (memory safety is unaffected);
+ *     dsgm_count_nonfinite checks a sequence for them.
  */
 #ifndef DSGM_H
 #define DSGM_H
@@ -356,6 +357,18 @@ const char* dsgm_last_error(void);
 
 /* ABI version: major*10000 + minor*100 + patch */
 int dsgm_version(void);
+
+/*
+ * Count the NaN and infinite intensities of T x H x W frames (addressed with
+ * the shape's strides, like every frames argument) into *count (device, one
+ * uint64, overwritten).  The update is defined for finite intensities; with
+ * others its branches are whatever the IEEE comparisons decide, so this is the
+ * check a caller can run on its input first.  Enqueues two kernels (one
+ * clears the counter) and nothing else, so it can be captured into a graph;
+ * the count is exact.  U8 frames always count 0.
+ */
+int dsgm_count_nonfinite(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                         uint64_t* count, hipStream_t stream);
 
 /* Flags of the launch-shape tuner: the optional outputs of the calls to tune */
 typedef enum {

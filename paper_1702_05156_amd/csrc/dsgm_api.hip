@@ -586,6 +586,24 @@ int dsgm_autotune_clear(void) {
   return ok();
 }
 
+int dsgm_count_nonfinite(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                         uint64_t* count, hipStream_t stream) {
+  int rc;
+  if (in_dtype < DSGM_IN_F64 || in_dtype > DSGM_IN_U8)
+    return fail(DSGM_E_DTYPE, "in_dtype = %d invalid", in_dtype);
+  if ((rc = check_shape(shape, in_size(in_dtype)))) return rc;
+  if (!count) return fail(DSGM_E_ARG, "count is NULL");
+  if (!aligned(count, 8)) return fail(DSGM_E_ALIGN, "count is not 8-byte aligned");
+  if (shape.T * shape.H * shape.W > 0 && !frames) return fail(DSGM_E_ARG, "frames is NULL");
+  if (frames && !aligned(frames, in_size(in_dtype)))
+    return fail(DSGM_E_ALIGN, "frames not aligned to %zu bytes", in_size(in_dtype));
+  dsgm::CountArgs a{shape.T, shape.H, shape.W, shape.row_stride, shape.frame_stride,
+                    reinterpret_cast<unsigned long long*>(count)};
+  const hipError_t e = dsgm::launch_count_nonfinite(frames, in_dtype, a, stream);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_count_nonfinite launch");
+  return ok();
+}
+
 int dsgm_gauss_weights(int32_t n, double sigma, double* weights) {
   if (n < 1 || n > 7 || n % 2 == 0) return fail(DSGM_E_ARG, "blur taps n = %d (odd, 1..7)", n);
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(DSGM_E_ARG, "sigma must be > 0");

@@ -89,6 +89,15 @@ hipError_t launch_grid(const GridArgs& a, int in_dtype, int acc, int b, hipStrea
 hipError_t launch_tune_fill(void* out, int in_dtype, int64_t n, uint64_t seed,
                             hipStream_t stream);
 
+// Count of the non-finite frame elements (dsgm_check.hip): clears *count,
+// then adds the NaN and infinite elements of the T x H x W frames.
+struct CountArgs {
+  int64_t T, H, W, row_stride, frame_stride;
+  unsigned long long* count;
+};
+hipError_t launch_count_nonfinite(const void* frames, int in_dtype, const CountArgs& a,
+                                  hipStream_t stream);
+
 // Logical tile of workgroup b of nb: the hardware deals workgroups to the 8
 // XCDs round-robin (b mod 8), each XCD with its own L2; this bijection gives
 // XCD k the k-th contiguous share of the tiles, so tiles that share input rows

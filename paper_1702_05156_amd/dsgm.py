@@ -128,6 +128,7 @@ def _load():
     lib.dsgm_status_string.restype = ctypes.c_char_p
     lib.dsgm_last_error.restype = ctypes.c_char_p
     lib.dsgm_set_launch.argtypes = [i32, i32]
+    lib.dsgm_count_nonfinite.argtypes = [vp, i32, Shape, vp, vp]
     lib.dsgm_autotune_bytes.argtypes = [i32, i32, Shape, i32]
     lib.dsgm_autotune_bytes.restype = ctypes.c_size_t
     lib.dsgm_autotune.argtypes = [i32, i32, Shape, i32, vp, ctypes.c_size_t,
@@ -138,7 +139,7 @@ def _load():
               "dsgm_backward", "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_version",
               "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
               "dsgm_forward_warped", "dsgm_forward_grid", "dsgm_autotune",
-              "dsgm_autotune_lookup", "dsgm_autotune_clear"):
+              "dsgm_autotune_lookup", "dsgm_autotune_clear", "dsgm_count_nonfinite"):
         getattr(lib, f).restype = ctypes.c_int
     del i64
     return lib
@@ -152,7 +153,7 @@ EXPORTS = ["dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
            "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_status_string", "dsgm_last_error",
            "dsgm_version", "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
            "dsgm_forward_warped", "dsgm_forward_grid", "dsgm_autotune_bytes", "dsgm_autotune",
-           "dsgm_autotune_lookup", "dsgm_autotune_clear"]
+           "dsgm_autotune_lookup", "dsgm_autotune_clear", "dsgm_count_nonfinite"]
 
 
 def _check(fn: str, rc: int):
@@ -321,6 +322,22 @@ def dsgm_forward(frames: torch.Tensor, state: State, params: Params, masks: torc
                             ctypes.byref(cs), _ptr(masks), _ptr(bg), _ptr(ckpt),
                             0 if ckpt is None else ckpt.numel(), int(ckpt_every), _ptr(codes),
                             _stream()))
+
+
+def dsgm_count_nonfinite(frames: torch.Tensor, count: torch.Tensor | None = None) -> torch.Tensor:
+    """Count the NaN and infinite elements of ``frames`` (T x H x W) into a
+    device int64 scalar (``count``, or a new one), asynchronously."""
+    if frames.dtype not in _IN_DTYPES:
+        raise TypeError(f"frames dtype {frames.dtype} not supported")
+    sh = _frames_shape(frames)
+    if count is None:
+        count = torch.empty((), dtype=torch.int64, device=frames.device)
+    elif count.dtype != torch.int64 or count.numel() != 1 or not count.is_cuda:
+        raise ValueError("count: need a CUDA int64 scalar")
+    _check("dsgm_count_nonfinite",
+           lib.dsgm_count_nonfinite(_ptr(frames), _IN_DTYPES[frames.dtype], sh, _ptr(count),
+                                    _stream()))
+    return count
 
 
 def dsgm_gauss_weights(n: int = 5, sigma: float = 1.0) -> list:

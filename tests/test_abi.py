@@ -349,3 +349,16 @@ def test_host_tables_are_thread_safe():
         t.join()
     assert not errors
     assert lib.dsgm_set_launch(0, 0) == 0
+
+
+def test_count_nonfinite_rejects_before_any_hip_call():
+    S = lambda T, H, W: dsgm.Shape(T, H, W, W, H * W)
+    fake = ctypes.c_void_p(256)
+    assert lib.dsgm_count_nonfinite(fake, 9, S(2, 3, 4), fake, None) == -3          # dtype
+    assert lib.dsgm_count_nonfinite(fake, 0, S(-1, 3, 4), fake, None) == -2         # shape
+    assert lib.dsgm_count_nonfinite(fake, 0, dsgm.Shape(2, 3, 4, 3, 12), fake, None) == -2
+    assert lib.dsgm_count_nonfinite(fake, 0, S(2, 3, 4), None, None) == -1          # no count
+    assert lib.dsgm_count_nonfinite(fake, 0, S(2, 3, 4), ctypes.c_void_p(260), None) == -4
+    assert lib.dsgm_count_nonfinite(None, 0, S(2, 3, 4), fake, None) == -1          # no frames
+    assert lib.dsgm_count_nonfinite(ctypes.c_void_p(258), 1, S(2, 3, 4), fake, None) == -4
+    assert b"frames" in lib.dsgm_last_error()
