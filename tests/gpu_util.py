@@ -62,3 +62,21 @@ def assert_bit_exact(name, got, want):
         idx = np.argwhere(bad)[:5]
         raise AssertionError(f"{name}: {int(bad.sum())} of {bad.size} differ; first at "
                              f"{idx.tolist()}: got {got[bad][:5]} want {want[bad][:5]}")
+
+
+def ckpt_payload(ck: torch.Tensor, T, H, W, K, elt_bytes) -> torch.Tensor:
+    """The defined bytes of a checkpoint buffer: per slot (the state before
+    frames 0, K, 2K, ...) four float planes of elt_bytes * H*W bytes and two
+    age planes of H*W bytes, each plane starting on a 256-byte boundary.  The
+    padding between planes is never written, so whole buffers are not
+    comparable."""
+    px = H * W
+    fpl = (px * elt_bytes + 255) // 256 * 256
+    apl = (px + 255) // 256 * 256
+    slot = 4 * fpl + 2 * apl
+    parts = []
+    for j in range((T + K - 1) // K):
+        b = j * slot
+        parts += [ck[b + i * fpl: b + i * fpl + px * elt_bytes] for i in range(4)]
+        parts += [ck[b + 4 * fpl + i * apl: b + 4 * fpl + i * apl + px] for i in range(2)]
+    return torch.cat(parts)

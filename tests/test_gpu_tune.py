@@ -95,7 +95,12 @@ def test_native_autotune_chooses_and_applies(in_dtype, acc_dtype, acc, flags, W)
     dsgm.dsgm_autotune_clear()
     ref, ref_st = _same_forward(fr, st, p, **kw)
     for k in ref:
-        assert torch.equal(tuned[k], ref[k]), k
+        if k == "ckpt":  # only the defined bytes (not the padding between planes)
+            eb = 8 if acc_dtype == torch.float64 else 4
+            assert torch.equal(G.ckpt_payload(tuned[k], T, H, W, 8, eb),
+                               G.ckpt_payload(ref[k], T, H, W, 8, eb))
+        else:
+            assert torch.equal(tuned[k], ref[k]), k
     for a, b in zip(tuned_st.planes(), ref_st.planes()):
         assert torch.equal(a, b)
 
