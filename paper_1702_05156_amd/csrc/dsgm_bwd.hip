@@ -25,8 +25,15 @@ namespace dsgm {
 
 namespace {
 
+// With FP32 state the kernel is compiled for at least 4 waves per SIMD (at most
+// 128 VGPRs), which fits without spills once the upstream gradients are loaded
+// in two halves (below): BF16 frames ran 4 % faster than at 3 waves, FP32
+// frames the same.  FP64 state keeps the compiler's choice: its tape alone
+// takes 64 VGPRs, and neither the split loads nor 3 waves per SIMD (which
+// spill) were faster.
 template <typename In, typename Acc, typename Io, int KC, bool HAS_GBG, bool HAS_GST>
-__global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Acc) == 4 ? 4 : 1)))
+bwd_kernel(const BwdArgs a) {
   __shared__ TableEntry<Acc> tbl[TABLE_SIZE];
   for (int i = threadIdx.x; i < TABLE_SIZE; i += blockDim.x)
     tbl[i] = make_entry<Acc>(i, a.weight_rule, a.age_max, Acc(a.var_init));
@@ -99,15 +106,28 @@ __global__ void __launch_bounds__(256) bwd_kernel(const BwdArgs a) {
           tape_m[i / 2] |= m << 16;
       }
     }
-    // the gradient loads reuse the frames' registers (dead after the replay)
+    // the gradient loads reuse the frames' registers (dead after the replay);
+    // with FP32 state the frames [LATE, KC) are loaded before the sweep and
+    // [0, LATE) once the sweep reaches frame LATE - 1 (fewer registers live)
+    constexpr int LATE = sizeof(Acc) == 4 ? KC / 2 : 0;
 #pragma unroll
-    for (int i = 0; i < KC; ++i) {
+    for (int i = LATE; i < KC; ++i) {
       gb[i] = Io(0);
       if (HAS_GBG && (FULL || i < len))
         gb[i] = *reinterpret_cast<const Io*>(gbg + (c0 + i) * fs_io + off_io);
     }
 #pragma unroll
     for (int i = KC - 1; i >= 0; --i) {
+      if constexpr (LATE > 0) {
+        if (i == LATE - 1) {
+#pragma unroll
+          for (int j = 0; j < LATE; ++j) {
+            gb[j] = Io(0);
+            if (HAS_GBG && (FULL || j < len))
+              gb[j] = *reinterpret_cast<const Io*>(gbg + (c0 + j) * fs_io + off_io);
+          }
+        }
+      }
       if (FULL || i < len) {
         const uint32_t m = (tape_m[i / 2] >> (16 * (i % 2))) & 0xFFFFu;
         const Acc gx = reverse_step<Acc, HAS_GBG>(adj, Acc(gb[i]), tape_d[i], int(m & 0x1FFu),
