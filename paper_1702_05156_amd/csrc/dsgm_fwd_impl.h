@@ -273,6 +273,21 @@ __global__ void __launch_bounds__(256) fwd_kernel(const FwdArgs a) {
   run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl);
 }
 
+// The first active lane's copy of v in every lane, as a value the compiler
+// knows to be the same across the wavefront (held in scalar registers).
+template <typename T>
+__device__ __forceinline__ T wave_uniform(const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "whole dwords");
+  union {
+    T t;
+    int w[sizeof(T) / 4];
+  } u;
+  u.t = v;
+#pragma unroll
+  for (int i = 0; i < int(sizeof(T) / 4); ++i) u.w[i] = __builtin_amdgcn_readfirstlane(u.w[i]);
+  return u.t;
+}
+
 // FLAGS may only hold F_BG and F_PRINTED (no codes, no checkpoints)
 template <typename In, typename Acc, typename Io, int P, int U, int FLAGS>
 __global__ void __launch_bounds__(256) batched_kernel(const BatchArgs a) {
@@ -287,10 +302,12 @@ __global__ void __launch_bounds__(256) batched_kernel(const BatchArgs a) {
     // counter has passed n_items
     unsigned long long item = 0;
     if (lane == 0) item = atomicAdd(a.counter, 1ull);
-    item = __shfl(item, 0, 64);
+    item = wave_uniform(item);
     if (item >= (unsigned long long)a.n_items) break;
-    const BatchItem it = a.items[item];
-    const BatchInst& I = a.inst[it.inst];
+    // the item and its instance are the same for the whole wavefront: scalar
+    // registers, not 30 vector registers per lane
+    const BatchItem it = wave_uniform(a.items[item]);
+    const BatchInst I = wave_uniform(a.inst[it.inst]);
     if (lane < it.count) {
       const int64_t g = int64_t(it.first_group) + lane;
       const int64_t h = g / I.groups_per_row;

@@ -77,9 +77,16 @@ def test_f64_adjoint_appendix_weights_bit_exact(in_dtype):
     G.assert_bit_exact("grad_var_init per pixel", px, ref["grad_var_init_px"])
 
 
-def test_adjoint_does_not_depend_on_checkpoint_interval():
+@pytest.mark.parametrize("in_dtype", [torch.float32, torch.bfloat16])
+def test_adjoint_does_not_depend_on_checkpoint_interval(in_dtype):
+    """FP32 state: the replay recomputes the forward's values exactly, so every
+    checkpoint interval gives the same bits.  The intervals cover chunks of
+    every kind the 32-frame tape has: full, shorter than the half loaded before
+    the sweep (1, 5, 10), longer than it (20, 25, 31), and segments longer than
+    the tape, whose later chunks replay a prefix (33, 45, 70)."""
     T, H, W, seed = 70, 8, 64, 22
-    res = [_gpu_fwd_bwd(seed, T, H, W, K, torch.float32, torch.float32)[2] for K in (1, 5, 32, 33, 70)]
+    res = [_gpu_fwd_bwd(seed, T, H, W, K, in_dtype, torch.float32)[2]
+           for K in (1, 5, 20, 31, 32, 33, 45, 70)]
     for r in res[1:]:
         assert torch.equal(r["grad_frames"], res[0]["grad_frames"])
         for a, b in zip(r["grad_state0"], res[0]["grad_state0"]):
