@@ -92,15 +92,18 @@ def test_grid_block_one_equals_the_pixel_forward():
         assert torch.equal(a, c)
 
 
+@pytest.mark.parametrize("T,H,W,b", [(100, 64, 128, 4), (37, 30, 45, 4), (37, 30, 45, 2)])
 @pytest.mark.parametrize("in_dtype", [torch.bfloat16, torch.float32])
-def test_grid_fp32_close_to_fp64(in_dtype):
+def test_grid_fp32_close_to_fp64(in_dtype, T, H, W, b):
     """FP32 state against the FP64 oracle on the same values: at most 1e-3 of
-    the blocks take a different decision anywhere; the others agree to 1e-5."""
-    T, H, W, b = 100, 64, 128, 4
+    the blocks, or one block, take a different decision anywhere; the others
+    agree to 1e-5.
+    The ragged shapes have partial edge blocks (the scalar load path) and an
+    odd frame count."""
     p, st, masks, bg, codes, x, st0 = _run(64, T, H, W, b, in_dtype, torch.float32)
     ref = oracle.forward_grid(x, st0, G.oracle_params(p), b)
     div = (codes.cpu().numpy().reshape(T, -1) != ref["codes"]).any(axis=0)
-    assert div.mean() <= 1e-3, div.mean()
+    assert div.sum() <= max(1, int(1e-3 * div.size)), div.mean()
     hs = G.state_to_host(st)
     ok = ~div
     for k in ("mean_a", "mean_c"):
