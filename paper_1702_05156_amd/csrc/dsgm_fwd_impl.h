@@ -274,18 +274,19 @@ __global__ void __launch_bounds__(256) fwd_kernel(const FwdArgs a) {
 }
 
 // The first active lane's copy of v in every lane, as a value the compiler
-// knows to be the same across the wavefront (held in scalar registers).
+// knows to be the same across the wavefront (held in scalar registers).  The
+// callers run with all 64 lanes active (256-thread workgroups, uniform control
+// flow), so the first active lane is lane 0.
 template <typename T>
 __device__ __forceinline__ T wave_uniform(const T& v) {
   static_assert(sizeof(T) % 4 == 0, "whole dwords");
-  union {
-    T t;
-    int w[sizeof(T) / 4];
-  } u;
-  u.t = v;
+  int w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
 #pragma unroll
-  for (int i = 0; i < int(sizeof(T) / 4); ++i) u.w[i] = __builtin_amdgcn_readfirstlane(u.w[i]);
-  return u.t;
+  for (int i = 0; i < int(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));
+  return out;
 }
 
 // FLAGS may only hold F_BG and F_PRINTED (no codes, no checkpoints)
