@@ -329,6 +329,43 @@ def test_fp64_matches_exact_until_near_tie(seed):
     assert checked > T * N // 2
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_fp64_margins_match_exact(seed):
+    """The oracle's three decision margins (squared distance minus threshold of
+    the A test, the C test and the background test; Sec. 2.3 and the
+    appendix's inner update) against exact rationals on dyadic data, for all
+    four combinations of weight and mask rule.  Both margins of the match
+    tests are compared on every step, including steps where A matched and the
+    C test decides nothing.  Until the first near tie the two runs take the
+    same decisions, so the FP64 margin may differ from the exact one only by
+    the rounding of a handful of operations on values of magnitude <= 8:
+    1e-12 absolute is thousands of ulps of slack and far below any wrong
+    threshold, sign or floor."""
+    T, N = 40, 16
+    x, st = _dyadic_case(100 + seed, T, N)
+    p = oracle.Params(theta_s=2.0, theta_d=4.0, var_init=0.5, var_floor=1 / 64, mask_floor=1 / 16,
+                      age_max=30, weight_rule=seed % 2, mask_rule=(seed // 2) % 2)
+    r = oracle.forward(x, st, p, margins=True)
+    ex = exact.forward([[Fraction(float(v)) for v in row] for row in x], _to_exact_state(st), p)
+    checked = a_matched = 0
+    for i in range(N):
+        for t in range(T):
+            ma, mc, md = ex["margins"][t][i]
+            code = ex["codes"][t][i]
+            if abs(ma) < 1e-9 or (not code & oracle.HIT_A and abs(mc) < 1e-9):
+                break
+            for k, m in enumerate((ma, mc, md)):
+                assert abs(r["margins"][t, i, k] - float(m)) <= 1e-12, (i, t, k)
+            # the sign of each margin is the decision the paper's comparison takes
+            assert bool(code & oracle.HIT_A) == (ma < 0)
+            if not code & oracle.HIT_A:
+                assert bool(code & oracle.HIT_C) == (mc < 0)
+            assert bool(code & oracle.FG) == (md > 0)
+            a_matched += bool(code & oracle.HIT_A)
+            checked += 1
+    assert checked > T * N // 2 and a_matched > T * N // 8
+
+
 def test_fp64_exact_when_arithmetic_is_exact():
     """A_max = 1 (w = u = 1/2) and data on a 1/16 grid over 8 frames: every FP64
     operation is exact, so the FP64 oracle must reproduce the exact-rational run
