@@ -80,3 +80,48 @@ def ckpt_payload(ck: torch.Tensor, T, H, W, K, elt_bytes) -> torch.Tensor:
         parts += [ck[b + i * fpl: b + i * fpl + px * elt_bytes] for i in range(4)]
         parts += [ck[b + 4 * fpl + i * apl: b + 4 * fpl + i * apl + px] for i in range(2)]
     return torch.cat(parts)
+
+
+def first_near_tie(ref, tol=1e-5) -> np.ndarray:
+    """Per pixel, the first frame at which the oracle takes a decision whose
+    FP64 margin (squared distance minus threshold) is within `tol` of zero:
+    the A test on every frame, the C test on frames where A did not match,
+    the background test on every frame.  T where there is none."""
+    m, c = ref["margins"], ref["codes"]
+    T = c.shape[0]
+    a_missed = (c & oracle.HIT_A) == 0
+    near = ((np.abs(m[..., 0]) <= tol) | (a_missed & (np.abs(m[..., 1]) <= tol)) |
+            (np.abs(m[..., 2]) <= tol))
+    return np.where(near.any(axis=0), near.argmax(axis=0), T)
+
+
+def certify_masks(masks_gpu, ref, tol=1e-5):
+    """Certification of a reduced-precision run from its masks alone (no
+    decision codes, so the launch under test is the one without them).  The
+    FP32 state error is far below `tol`, so the run must take the oracle's
+    decisions until the oracle's first near tie of a pixel: masks identical
+    before that frame, and identical throughout on pixels with no near tie.
+    Returns (clear, mask_differs): pixels with no near tie, and pixels
+    whose masks differ somewhere."""
+    masks_gpu = np.asarray(masks_gpu)
+    T = masks_gpu.shape[0]
+    first = first_near_tie(ref, tol)
+    diff = masks_gpu != ref["masks"]
+    early = diff & (np.arange(T)[:, None] < first[None, :])
+    if early.any():
+        t, j = np.argwhere(early)[0]
+        raise AssertionError(f"mask differs at frame {t}, sample pixel {j}, before its first "
+                             f"near tie (frame {first[j]}): margins {ref['margins'][t, j]}")
+    return first == T, diff.any(axis=0)
+
+
+def assert_state_close(hs, ref, sel, var_init, tol=1e-5):
+    """Final model state of the reduced-precision run on the pixels `sel`:
+    means within tol, variances within tol * max(v, var_init), ages equal."""
+    for k in ("mean_a", "mean_c"):
+        assert np.max(np.abs(hs[k][sel] - ref[k][sel]), initial=0.0) <= tol, k
+    for k in ("var_a", "var_c"):
+        d = np.abs(hs[k][sel] - ref[k][sel]) / np.maximum(ref[k][sel], var_init)
+        assert np.max(d, initial=0.0) <= tol, k
+    for k in ("age_a", "age_c"):
+        assert_bit_exact(k, hs[k][sel], ref[k][sel])

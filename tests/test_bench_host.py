@@ -37,6 +37,12 @@ def test_roof_ceilings_valu_binding():
     c = r["ceilings"]
     assert c["binding"] == "valu"
     assert c["frac_of_binding"] == pytest.approx(1e12 / (256 * 64 * 2.4e9 / 22), abs=1e-4)
+    # the line names the binding ceiling: ALU, in lane-ops/s, HBM figures kept aside
+    r0 = bench.roof(3e9, 1.0, 1e9, 22)
+    assert r0["bound"] == "alu" and r0["unit"] == "T lane-ops/s"
+    assert r0["achieved"] == pytest.approx(22.0) and r0["peak"] == pytest.approx(39.3216, abs=1e-3)
+    assert r0["frac"] == pytest.approx(c["frac_of_binding"])
+    assert r0["hbm"]["bound"] == "hbm" and r0["hbm"]["achieved"] == pytest.approx(3000.0)
     # in FP32 the VALU ceiling doubles (3.57 T elt/s) and HBM binds
     c = bench.roof(3e9, 1.0, 1e9, 22, fp32=True)["ceilings"]
     assert c["arithmetic"] == "f32" and c["binding"] == "hbm"

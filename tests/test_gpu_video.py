@@ -99,3 +99,47 @@ def test_video_f64_adjoint_bit_exact():
                            ref["grad_state0"][i])
     assert float(r["grad_var_init"].item()) == pytest.approx(ref["grad_var_init"], rel=1e-15,
                                                                abs=1e-300)
+
+
+@pytest.mark.slow
+def test_full_size_video_bf16_fp32_certified():
+    """The benchmark's video leg at full size: 1920x2560 x 500 frames of the
+    structured video (seed 1), BF16 frames, FP32 state from frame 0, masks
+    only (the launch it times).  On realistic input close to 1e-3 of the
+    pixels take a different decision from the FP64 path somewhere; every
+    pixel whose masks differ from the FP64 path's (up to 2048 of them, plus
+    2048 random pixels) is certified against the oracle from the masks alone:
+    identical masks until the oracle's first near tie (FP64 margin <= 1e-5),
+    and pixels with no near tie identical throughout, final state within
+    1e-5."""
+    T, H, W, seed = 500, 1920, 2560, 1
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.video(seed, T, H, W, torch.bfloat16)
+    st = _init_state_dev(fr, torch.float32, p)
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    dsgm.dsgm_forward(fr, st, p, masks)
+    f64 = fr.double()
+    st64 = _init_state_dev(f64, torch.float64, p)
+    m64 = torch.empty_like(masks)
+    dsgm.dsgm_forward(f64, st64, p, m64)
+    torch.cuda.synchronize()
+    del f64, st64
+    differs_all = (masks != m64).view(T, -1).any(dim=0)
+    frac = float(differs_all.float().mean().item())
+    assert frac <= 1e-3, frac
+    bad = torch.nonzero(differs_all).view(-1).cpu().numpy()
+    rng = np.random.default_rng(1)
+    pick = bad if bad.size <= 2048 else rng.choice(bad, 2048, replace=False)
+    pix = np.unique(np.concatenate([pick, rng.choice(H * W, 2048, replace=False)]))
+    x = synth.video(seed, T, H, W, pix=pix)
+    s0 = _init_state_host(x[0], p)
+    s0["var_a"] = s0["var_c"] = np.full(pix.size, float(np.float32(p.var_init)))
+    ref = oracle.forward(x, s0, G.oracle_params(p), margins=True)
+    pt = torch.as_tensor(pix, device="cuda")
+    clear, differs = G.certify_masks(masks.view(T, -1)[:, pt].cpu().numpy(), ref)
+    assert not differs[clear].any()
+    hs = {k: v[pix] for k, v in G.state_to_host(st).items()}
+    G.assert_state_close(hs, ref, clear, p.var_init)
+    # the sample holds the differing pixels: the certification saw them
+    assert differs[np.isin(pix, pick)].all()
+    del fr, masks, m64
