@@ -105,9 +105,13 @@ def test_video_f64_adjoint_bit_exact():
 def test_full_size_video_bf16_fp32_certified():
     """The benchmark's video leg at full size: 1920x2560 x 500 frames of the
     structured video (seed 1), BF16 frames, FP32 state from frame 0, masks
-    only (the launch it times).  On realistic input close to 1e-3 of the
-    pixels take a different decision from the FP64 path somewhere; every
-    pixel whose masks differ from the FP64 path's (up to 2048 of them, plus
+    only (the launch it times).  The diverged fraction of the tolerance
+    contract counts pixels whose match, reset or swap decisions differ from
+    the FP64 path somewhere; it is taken from the same pass with decision
+    codes, which must give the timed launch's bits, and must stay <= 1e-3.
+    Background-test near ties flip single masks without any such decision
+    differing, so more pixels show a mask difference (about 2e-3 of them on
+    this input); every one of those that is sampled (up to 2048 of them, plus
     2048 random pixels) is certified against the oracle from the masks alone:
     identical masks until the oracle's first near tie (FP64 margin <= 1e-5),
     and pixels with no near tie identical throughout, final state within
@@ -116,17 +120,27 @@ def test_full_size_video_bf16_fp32_certified():
     p = dsgm.dsgm_params_default(2.0)
     fr = sdev.video(seed, T, H, W, torch.bfloat16)
     st = _init_state_dev(fr, torch.float32, p)
+    st_cd = st.clone()
     masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
     dsgm.dsgm_forward(fr, st, p, masks)
+    m_cd, c_cd = torch.empty_like(masks), torch.empty_like(masks)
+    dsgm.dsgm_forward(fr, st_cd, p, m_cd, codes=c_cd)
+    torch.cuda.synchronize()
+    assert torch.equal(m_cd, masks)
+    for a, b in zip(st_cd.planes(), st.planes()):
+        assert torch.equal(a, b)
+    del m_cd, st_cd
     f64 = fr.double()
     st64 = _init_state_dev(f64, torch.float64, p)
-    m64 = torch.empty_like(masks)
-    dsgm.dsgm_forward(f64, st64, p, m64)
+    m64, c64 = torch.empty_like(masks), torch.empty_like(masks)
+    dsgm.dsgm_forward(f64, st64, p, m64, codes=c64)
     torch.cuda.synchronize()
     del f64, st64
+    diverged = ((c_cd & 15) != (c64 & 15)).view(T, -1).any(dim=0)
+    div_frac = float(diverged.float().mean().item())
+    assert div_frac <= 1e-3, div_frac
+    del c_cd, c64
     differs_all = (masks != m64).view(T, -1).any(dim=0)
-    frac = float(differs_all.float().mean().item())
-    assert frac <= 1e-3, frac
     bad = torch.nonzero(differs_all).view(-1).cpu().numpy()
     rng = np.random.default_rng(1)
     pick = bad if bad.size <= 2048 else rng.choice(bad, 2048, replace=False)
