@@ -212,6 +212,29 @@ int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, 
                   hipStream_t stream);
 
 /*
+ * dsgm_backward for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * arguments without the workspace, the same kernels and bit-identical results.
+ * The per-pixel terms and partial sums live in a buffer of the library's own,
+ * 8 * (DSGM_NOALLOC_MAX_PIXELS + 512) bytes (64 MiB + 4 KiB) on each device
+ * the function runs on, held until the process ends; its device address is
+ * looked up on the first call on a device (with that device current).
+ *   H * W > DSGM_NOALLOC_MAX_PIXELS returns DSGM_E_WORKSPACE (before any HIP
+ *   call); every other argument and error is as for dsgm_backward.
+ * Nothing is allocated by the call.  Every call on one device shares that
+ * device's buffer: calls that may overlap on one device (different streams,
+ * or host threads without ordering) race and must be serialised by the
+ * caller; calls ordered on one stream are safe.
+ */
+#define DSGM_NOALLOC_MAX_PIXELS (1LL << 23) /* 8,388,608 pixels: 2160 x 3840 fits */
+int dsgm_backward_noalloc(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                          dsgm_acc acc, const dsgm_params* params /* host */, const void* ckpt,
+                          size_t ckpt_bytes, int32_t ckpt_every, const void* grad_bg,
+                          const dsgm_grad_state* grad_state_T /* host, or NULL */,
+                          void* grad_frames, dsgm_grad_state* grad_state0 /* host */,
+                          double* grad_var_init, hipStream_t stream);
+
+/*
  * Frame preprocessing (Sec. 2.1; serial and GPU versions in Sec. 3.1.1 and
  * 3.3.1): a separable blur -- the n-tap kernel applied along rows, then along
  * columns of the row-blurred frame, each sum taken from 0 in tap order -- then

@@ -837,23 +837,25 @@ size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc) {
   return size_t(pad256(shape.H * shape.W * 8)) + dsgm::reduce_workspace_bytes();
 }
 
-int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
-                  const dsgm_params* params, const void* ckpt, size_t ckpt_bytes,
-                  int32_t ckpt_every, const void* grad_bg, const dsgm_grad_state* grad_state_T, void* grad_frames,
-                  dsgm_grad_state* grad_state0, double* grad_var_init, void* workspace,
-                  size_t workspace_bytes, hipStream_t stream) {
+namespace {
+
+// Argument checks of both adjoint entry points, all before any HIP call.
+// `workspace` is the caller's buffer (dsgm_backward) or NULL when the library
+// brings its own (dsgm_backward_noalloc).
+int backward_validate(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                      dsgm_acc acc, const dsgm_params* params, const void* ckpt,
+                      size_t ckpt_bytes, int32_t ckpt_every, const void* grad_bg,
+                      const dsgm_grad_state* grad_state_T, const void* grad_frames,
+                      const dsgm_grad_state* grad_state0, const double* grad_var_init,
+                      const void* workspace) {
   int rc;
   if ((rc = check_types(in_dtype, acc))) return rc;
   if ((rc = check_params(params))) return rc;
-  const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
+  const size_t ie = in_size(in_dtype), oe = io_size(acc);
   if ((rc = check_shape(shape, ie > oe ? ie : oe))) return rc;
   const int64_t px = shape.H * shape.W;
   const int64_t n = shape.T * px;
   if (!grad_var_init) return fail(DSGM_E_ARG, "grad_var_init is NULL");
-  if (!workspace) return fail(DSGM_E_ARG, "workspace is NULL");
-  const size_t need = dsgm_workspace_bytes(shape, acc);
-  if (workspace_bytes < need)
-    return fail(DSGM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
   if (px > 0) {
     if (!grad_state0 || !grad_state0->mean_a || !grad_state0->var_a || !grad_state0->mean_c ||
         !grad_state0->var_c)
@@ -884,9 +886,21 @@ int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, 
   for (int i = 0; i < 14; ++i)
     if (ptrs[i] && !aligned(ptrs[i], elem[i]))
       return fail(DSGM_E_ALIGN, "pointer argument %d is not aligned to %zu bytes", i, elem[i]);
+  return DSGM_OK;
+}
 
-  double* gvi_px = static_cast<double*>(workspace);
-  double* partial = reinterpret_cast<double*>(static_cast<char*>(workspace) + pad256(px * 8));
+// The launches of the adjoint (arguments already validated), with the
+// per-pixel d/d(var_init) terms at gvi_px (H*W doubles, device) and the
+// reduction's partial sums at partial (dsgm::reduce_workspace_bytes() bytes,
+// device).  Every pixel's term is written by the adjoint kernel and every
+// partial by the reduction, so neither buffer needs clearing.
+int backward_launch(const char* fn, const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                    dsgm_acc acc, const dsgm_params* params, const void* ckpt,
+                    int32_t ckpt_every, const void* grad_bg, const dsgm_grad_state* grad_state_T,
+                    void* grad_frames, dsgm_grad_state* grad_state0, double* grad_var_init,
+                    double* gvi_px, double* partial, hipStream_t stream) {
+  const size_t ae = acc_size(acc);
+  const int64_t px = shape.H * shape.W;
   hipError_t e;
   if (px > 0) {
     dsgm::BwdArgs a;
@@ -924,11 +938,90 @@ int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, 
     a.weight_rule = params->weight_rule;
     a.mask_rule = params->mask_rule;
     e = dsgm::launch_backward(a, in_dtype, acc, stream);
-    if (e != hipSuccess) return hip_fail(e, "dsgm_backward launch");
+    if (e != hipSuccess) return hip_fail(e, fn);
   }
   e = dsgm::launch_reduce(gvi_px, px, partial, grad_var_init, stream);
-  if (e != hipSuccess) return hip_fail(e, "dsgm_backward reduction launch");
+  if (e != hipSuccess) return hip_fail(e, fn);
   return ok();
+}
+
+// The library's own buffer for the adjoint entry point that allocates
+// nothing: room for DSGM_NOALLOC_MAX_PIXELS per-pixel terms and the
+// reduction's partial sums.  Each device that runs the library holds one copy
+// until the process ends.  Host code never passes this name to a kernel: it
+// stands for a host-side shadow, not the device address; scratch_ptr() returns
+// the device address of the current device's copy.
+constexpr int64_t kScratchDoubles = int64_t(DSGM_NOALLOC_MAX_PIXELS) + 512;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device (with that
+// device current) and kept.
+int scratch_ptr(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "dsgm_backward_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(DSGM_E_UNSUPPORTED, "dsgm_backward_noalloc: device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "dsgm_backward_noalloc: hipGetSymbolAddress");
+    if (!p) return fail(DSGM_E_HIP, "dsgm_backward_noalloc: no device address for the scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[dev]);
+  return DSGM_OK;
+}
+
+}  // namespace
+
+int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, dsgm_acc acc,
+                  const dsgm_params* params, const void* ckpt, size_t ckpt_bytes,
+                  int32_t ckpt_every, const void* grad_bg, const dsgm_grad_state* grad_state_T, void* grad_frames,
+                  dsgm_grad_state* grad_state0, double* grad_var_init, void* workspace,
+                  size_t workspace_bytes, hipStream_t stream) {
+  int rc;
+  if ((rc = backward_validate(frames, in_dtype, shape, acc, params, ckpt, ckpt_bytes, ckpt_every,
+                              grad_bg, grad_state_T, grad_frames, grad_state0, grad_var_init,
+                              workspace)))
+    return rc;
+  if (!workspace) return fail(DSGM_E_ARG, "workspace is NULL");
+  const size_t need = dsgm_workspace_bytes(shape, acc);
+  if (workspace_bytes < need)
+    return fail(DSGM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
+  const int64_t px = shape.H * shape.W;
+  double* gvi_px = static_cast<double*>(workspace);
+  double* partial = reinterpret_cast<double*>(static_cast<char*>(workspace) + pad256(px * 8));
+  return backward_launch("dsgm_backward launch", frames, in_dtype, shape, acc, params, ckpt,
+                         ckpt_every, grad_bg, grad_state_T, grad_frames, grad_state0,
+                         grad_var_init, gvi_px, partial, stream);
+}
+
+int dsgm_backward_noalloc(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
+                          dsgm_acc acc, const dsgm_params* params, const void* ckpt,
+                          size_t ckpt_bytes, int32_t ckpt_every, const void* grad_bg,
+                          const dsgm_grad_state* grad_state_T, void* grad_frames,
+                          dsgm_grad_state* grad_state0, double* grad_var_init,
+                          hipStream_t stream) {
+  int rc;
+  if ((rc = backward_validate(frames, in_dtype, shape, acc, params, ckpt, ckpt_bytes, ckpt_every,
+                              grad_bg, grad_state_T, grad_frames, grad_state0, grad_var_init,
+                              nullptr)))
+    return rc;
+  const int64_t px = shape.H * shape.W;
+  if (px > int64_t(DSGM_NOALLOC_MAX_PIXELS))
+    return fail(DSGM_E_WORKSPACE, "dsgm_backward_noalloc: H*W = %lld pixels, at most %lld",
+                (long long)px, (long long)DSGM_NOALLOC_MAX_PIXELS);
+  double* base = nullptr;
+  if ((rc = scratch_ptr(&base))) return rc;
+  return backward_launch("dsgm_backward_noalloc launch", frames, in_dtype, shape, acc, params,
+                         ckpt, ckpt_every, grad_bg, grad_state_T, grad_frames, grad_state0,
+                         grad_var_init, base, base + int64_t(DSGM_NOALLOC_MAX_PIXELS), stream);
 }
 
 size_t dsgm_batch_plan_bytes(const dsgm_instance* instances, int32_t n, dsgm_in_dtype in_dtype,

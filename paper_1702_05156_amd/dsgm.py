@@ -119,6 +119,9 @@ def _load():
     lib.dsgm_backward.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params), vp, sz, i32, vp,
                                   ctypes.POINTER(_GradState), vp, ctypes.POINTER(_GradState), vp,
                                   vp, sz, vp]
+    lib.dsgm_backward_noalloc.argtypes = [vp, i32, Shape, i32, ctypes.POINTER(Params), vp, sz,
+                                          i32, vp, ctypes.POINTER(_GradState), vp,
+                                          ctypes.POINTER(_GradState), vp, vp]
     lib.dsgm_batch_plan_bytes.argtypes = [ctypes.POINTER(Instance), i32, i32, i32]
     lib.dsgm_batch_plan_bytes.restype = ctypes.c_size_t
     lib.dsgm_plan_batched.argtypes = [ctypes.POINTER(Instance), i32, i32, i32, vp, ctypes.c_size_t,
@@ -136,7 +139,7 @@ def _load():
     lib.dsgm_autotune_lookup.argtypes = [i32, i32, Shape, i32, ctypes.POINTER(ctypes.c_int32)]
     lib.dsgm_autotune_clear.argtypes = []
     for f in ("dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
-              "dsgm_backward", "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_version",
+              "dsgm_backward", "dsgm_backward_noalloc", "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_version",
               "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
               "dsgm_forward_warped", "dsgm_forward_grid", "dsgm_autotune",
               "dsgm_autotune_lookup", "dsgm_autotune_clear", "dsgm_count_nonfinite"):
@@ -153,7 +156,11 @@ EXPORTS = ["dsgm_params_default", "dsgm_state_init_from_frame", "dsgm_forward",
            "dsgm_plan_batched", "dsgm_forward_batched", "dsgm_status_string", "dsgm_last_error",
            "dsgm_version", "dsgm_set_launch", "dsgm_gauss_weights", "dsgm_forward_filtered",
            "dsgm_forward_warped", "dsgm_forward_grid", "dsgm_autotune_bytes", "dsgm_autotune",
-           "dsgm_autotune_lookup", "dsgm_autotune_clear", "dsgm_count_nonfinite"]
+           "dsgm_autotune_lookup", "dsgm_autotune_clear", "dsgm_count_nonfinite",
+           "dsgm_backward_noalloc"]
+
+# largest H*W dsgm_backward_noalloc accepts (the library's own buffer)
+NOALLOC_MAX_PIXELS = 1 << 23
 
 
 def _check(fn: str, rc: int):
@@ -474,6 +481,36 @@ def dsgm_backward(frames: torch.Tensor, params: Params, ckpt: torch.Tensor, ckpt
                              ctypes.byref(gsT) if gsT is not None else None, _ptr(grad_frames),
                              ctypes.byref(gs0) if gs0 is not None else None, _ptr(grad_var_init),
                              _ptr(workspace), workspace.numel(), _stream()))
+
+
+def dsgm_backward_noalloc(frames: torch.Tensor, params: Params, ckpt: torch.Tensor,
+                          ckpt_every: int, acc: int, grad_bg, grad_state_T,
+                          grad_frames: torch.Tensor, grad_state0,
+                          grad_var_init: torch.Tensor) -> None:
+    """dsgm_backward without a workspace: the library uses a buffer of its own
+    on the current device (H*W <= NOALLOC_MAX_PIXELS).  Calls that overlap on
+    one device race on that buffer."""
+    if frames.dtype not in _IN_DTYPES:
+        raise TypeError(f"frames dtype {frames.dtype} not supported")
+    sh = _frames_shape(frames)
+    adt = ACC_TORCH[acc]
+    _same_layout("grad_bg", grad_bg, frames, adt)
+    _same_layout("grad_frames", grad_frames, frames, adt)
+    gsT = _planes4("grad_state_T", grad_state_T, sh.H, sh.W, adt)
+    gs0 = _planes4("grad_state0", grad_state0, sh.H, sh.W, adt)
+    if grad_var_init.dtype != torch.float64 or not grad_var_init.is_cuda or grad_var_init.numel() != 1:
+        raise ValueError("grad_var_init: need a one-element float64 CUDA tensor")
+    if ckpt is not None and (ckpt.dtype != torch.uint8 or not ckpt.is_cuda):
+        raise ValueError("ckpt: need a CUDA uint8 tensor")
+    _check("dsgm_backward_noalloc",
+           lib.dsgm_backward_noalloc(_ptr(frames), _IN_DTYPES[frames.dtype], sh, acc,
+                                     ctypes.byref(params), _ptr(ckpt),
+                                     0 if ckpt is None else ckpt.numel(), int(ckpt_every),
+                                     _ptr(grad_bg),
+                                     ctypes.byref(gsT) if gsT is not None else None,
+                                     _ptr(grad_frames),
+                                     ctypes.byref(gs0) if gs0 is not None else None,
+                                     _ptr(grad_var_init), _stream()))
 
 
 # ------------------------------------------------------------------ convenience

@@ -150,6 +150,33 @@ def test_backward_validation():
     assert lib.dsgm_workspace_bytes(sh, 9) == 0
 
 
+def _bwd_na(frames=FAKE, shape=(4, 8, 8, 8, 64), ckpt=FAKE, K=2, gfr=FAKE, gs0="ok", gvi=FAKE,
+            acc=0, in_dtype=0, ckpt_bytes=1 << 40):
+    p = dsgm.dsgm_params_default(2.0)
+    g = dsgm._GradState(FAKE, FAKE, FAKE, FAKE) if gs0 == "ok" else gs0
+    return lib.dsgm_backward_noalloc(frames, in_dtype, dsgm.Shape(*shape), acc, ctypes.byref(p),
+                                     ckpt, ckpt_bytes, K, None, None, gfr,
+                                     ctypes.byref(g) if g is not None else None, gvi, None)
+
+
+def test_backward_noalloc_validation():
+    """The entry point without a workspace rejects what dsgm_backward rejects,
+    and frames larger than its own buffer, before any HIP call."""
+    assert _bwd_na(gvi=None) == -1
+    assert _bwd_na(ckpt=None) == -1
+    assert _bwd_na(K=0) == -1
+    assert _bwd_na(gfr=None) == -1
+    assert _bwd_na(gs0=None) == -1
+    assert _bwd_na(ckpt_bytes=1000) == -5
+    assert _bwd_na(frames=FAKE + 3) == -4
+    assert _bwd_na(in_dtype=0, acc=1) == -3
+    big = dsgm.NOALLOC_MAX_PIXELS
+    # one pixel over the limit: 2^23 + 1 = 3 * 2796203 (frames of one row)
+    assert _bwd_na(shape=(1, 1, big + 1, big + 1, big + 1)) == -5
+    assert b"at most" in lib.dsgm_last_error()
+    assert _bwd_na(shape=(1, 3, 2796203, 2796203, 3 * 2796203)) == -5
+
+
 def _inst(T=4, H=8, W=8, ptr=FAKE, bg=None):
     return dsgm.Instance(dsgm.Shape(T, H, W, W, H * W), ptr, _state(ptr), ptr, bg)
 
