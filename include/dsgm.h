@@ -75,8 +75,18 @@ typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2, DSGM_IN_U8 = 
  *             value converted to an integer with its fraction dropped and
  *             limited to [0, 255] (var_init too); the tests, the swap and the
  *             mask see the stored values.  dsgm_forward (masks, codes) and
- *             dsgm_state_init_from_frame only; other calls return DSGM_E_DTYPE */
-typedef enum { DSGM_ACC_F64 = 0, DSGM_ACC_F32 = 1, DSGM_ACC_F64_IO32 = 2, DSGM_ACC_U8 = 3 } dsgm_acc;
+ *             dsgm_state_init_from_frame only; other calls return DSGM_E_DTYPE
+ *   F32X2     compensated single precision (F32/BF16 frames): each state value
+ *             is an unevaluated sum hi + lo of two floats (|lo| <= ulp(hi)/2),
+ *             stored as interleaved (hi, lo) pairs, 8 bytes per value; every
+ *             operation is formed from error-free FP32 transformations (about
+ *             48 significant bits), so state and decisions follow the FP64
+ *             evaluation to about 1e-13, at FP32 instruction rates; bg and
+ *             gradient arrays are FP32 (hi + lo rounded once).
+ *             dsgm_forward, dsgm_backward(_noalloc), dsgm_state_init_from_frame
+ *             and the tuner; other calls return DSGM_E_DTYPE */
+typedef enum { DSGM_ACC_F64 = 0, DSGM_ACC_F32 = 1, DSGM_ACC_F64_IO32 = 2, DSGM_ACC_U8 = 3,
+               DSGM_ACC_F32X2 = 4 } dsgm_acc;
 
 /* learning weight of a model of age a: Sec. 2.2 gives 1/(a+1); the appendix
  * computes 1/a.  The complementary weight is 1 - w in the accumulation type. */

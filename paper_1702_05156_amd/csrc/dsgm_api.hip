@@ -72,6 +72,9 @@ int check_params(const dsgm_params* p) {
 int check_types(int in_dtype, int acc) {
   if (in_dtype < DSGM_IN_F64 || in_dtype > DSGM_IN_BF16)
     return fail(DSGM_E_DTYPE, "in_dtype = %d invalid", in_dtype);
+  if (acc == DSGM_ACC_F32X2)
+    return fail(DSGM_E_DTYPE, "F32X2 state: dsgm_forward, dsgm_backward and the state "
+                              "initialisation only");
   if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32)
     return fail(DSGM_E_DTYPE, "acc = %d invalid", acc);
   if (acc != DSGM_ACC_F64 && in_dtype == DSGM_IN_F64)
@@ -79,13 +82,25 @@ int check_types(int in_dtype, int acc) {
   return DSGM_OK;
 }
 
-// as check_types, and also the 8-bit as-run pair (U8 frames with U8 state),
+// as check_types, and also the compensated pair state (F32X2, with F32 or BF16
+// frames), which dsgm_forward, dsgm_backward and the state initialisation
+// implement
+int check_types_x2(int in_dtype, int acc) {
+  if (acc == DSGM_ACC_F32X2) {
+    if (in_dtype != DSGM_IN_F32 && in_dtype != DSGM_IN_BF16)
+      return fail(DSGM_E_DTYPE, "F32X2 state needs F32 or BF16 frames");
+    return DSGM_OK;
+  }
+  return check_types(in_dtype, acc);
+}
+
+// as check_types_x2, and also the 8-bit as-run pair (U8 frames with U8 state),
 // which only dsgm_forward and dsgm_state_init_from_frame implement
 int check_types_u8(int in_dtype, int acc) {
   if (in_dtype == DSGM_IN_U8 && acc == DSGM_ACC_U8) return DSGM_OK;
   if (in_dtype == DSGM_IN_U8 || acc == DSGM_ACC_U8)
     return fail(DSGM_E_DTYPE, "U8 frames and U8 state go together");
-  return check_types(in_dtype, acc);
+  return check_types_x2(in_dtype, acc);
 }
 
 // the 8-bit storage rule applied to a parameter (var_init of a reset model)
@@ -267,7 +282,9 @@ int dsgm_params_default(dsgm_params* p, double intensity_range, int32_t mask_rul
 }
 
 size_t dsgm_ckpt_bytes(dsgm_shape shape, dsgm_acc acc, int32_t ckpt_every) {
-  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32) return 0;
+  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32 &&
+      acc != DSGM_ACC_F32X2)
+    return 0;
   if (ckpt_every < 1 || shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;
   const int64_t n = (shape.T + ckpt_every - 1) / ckpt_every;
   const int64_t px = shape.H * shape.W;
@@ -832,7 +849,9 @@ int dsgm_forward_grid(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape sha
 }
 
 size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc) {
-  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32) return 0;
+  if (acc != DSGM_ACC_F64 && acc != DSGM_ACC_F32 && acc != DSGM_ACC_F64_IO32 &&
+      acc != DSGM_ACC_F32X2)
+    return 0;
   if (shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;
   return size_t(pad256(shape.H * shape.W * 8)) + dsgm::reduce_workspace_bytes();
 }
@@ -849,7 +868,7 @@ int backward_validate(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape sha
                       const dsgm_grad_state* grad_state0, const double* grad_var_init,
                       const void* workspace) {
   int rc;
-  if ((rc = check_types(in_dtype, acc))) return rc;
+  if ((rc = check_types_x2(in_dtype, acc))) return rc;
   if ((rc = check_params(params))) return rc;
   const size_t ie = in_size(in_dtype), oe = io_size(acc);
   if ((rc = check_shape(shape, ie > oe ? ie : oe))) return rc;

@@ -47,12 +47,8 @@ bwd_kernel(const BwdArgs a) {
   const uint32_t off_in = foff * uint32_t(sizeof(In));
   const uint32_t off_io = foff * uint32_t(sizeof(Io));
 
-  StepConsts<Acc> k;
-  k.theta_s = Acc(a.theta_s);
-  k.theta_d = Acc(a.theta_d);
-  k.var_init = Acc(a.var_init);
-  k.ts_vf = k.theta_s * Acc(a.var_floor);
-  k.td_mf = k.theta_d * Acc(a.mask_floor);
+  const StepConsts<Acc> k =
+      step_consts<Acc>(a.theta_s, a.theta_d, a.var_init, a.var_floor, a.mask_floor);
 
   const char* __restrict__ frames = static_cast<const char*>(a.frames);
   const char* __restrict__ gbg = static_cast<const char*>(a.grad_bg);
@@ -281,6 +277,9 @@ hipError_t launch_backward(const BwdArgs& a, int in_dtype, int acc, hipStream_t 
   } else if (acc == 2) {
     if (in_dtype == 1) return launch_bwd_k<float, double, float, 32>(a, stream);
     if (in_dtype == 2) return launch_bwd_k<bf16_t, double, float, 32>(a, stream);
+  } else if (acc == 4) {
+    if (in_dtype == 1) return launch_bwd_k<float, f32x2, float, 32>(a, stream);
+    if (in_dtype == 2) return launch_bwd_k<bf16_t, f32x2, float, 32>(a, stream);
   }
   return hipErrorInvalidValue;
 }

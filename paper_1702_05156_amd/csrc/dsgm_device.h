@@ -23,11 +23,14 @@
 // With Acc = double every product and sum is rounded on its own (the library is
 // built with -ffp-contract=off), so results are bit-identical to a scalar FP64
 // evaluation in the paper's order.  With Acc = float the two blends use fused
-// multiply-adds.
+// multiply-adds.  With Acc = f32x2 (compensated single precision, see
+// dsgm_f32x2.h) the step has its own form, step_core_x2().
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "dsgm_f32x2.h"
 
 namespace dsgm {
 
@@ -55,25 +58,60 @@ struct StepConsts {
 // both rounded in the accumulation type; age 0 (never valid) maps to w = 1.
 template <typename Acc>
 __device__ inline TableEntry<Acc> make_entry(int i, int weight_rule, int age_max, Acc var_init) {
-  TableEntry<Acc> e;
-  if (i == RESET_SLOT) {
-    e.u = Acc(0);
-    e.w = Acc(1);
-    e.r = var_init;
-    e.next = 1;
+  if constexpr (is_f32x2<Acc>::value) {
+    // the FP64 weights, each split into the nearest pair
+    const TableEntry<double> d = make_entry<double>(i, weight_rule, age_max, double(var_init));
+    TableEntry<f32x2> e;
+    e.u = f32x2(d.u);
+    e.w = f32x2(d.w);
+    e.r = i == RESET_SLOT ? var_init : f32x2(0.f);
+    e.next = d.next;
+    return e;
+  } else {
+    TableEntry<Acc> e;
+    if (i == RESET_SLOT) {
+      e.u = Acc(0);
+      e.w = Acc(1);
+      e.r = var_init;
+      e.next = 1;
+      return e;
+    }
+    const Acc one = Acc(1);
+    Acc w;
+    if (weight_rule == 1)
+      w = i == 0 ? one : one / Acc(i);
+    else
+      w = one / (Acc(i) + one);
+    e.w = w;
+    e.u = one - w;
+    e.r = Acc(0);
+    e.next = i + 1 < age_max ? i + 1 : age_max;
     return e;
   }
-  const Acc one = Acc(1);
-  Acc w;
-  if (weight_rule == 1)
-    w = i == 0 ? one : one / Acc(i);
-  else
-    w = one / (Acc(i) + one);
-  e.w = w;
-  e.u = one - w;
-  e.r = Acc(0);
-  e.next = i + 1 < age_max ? i + 1 : age_max;
-  return e;
+}
+
+// The per-launch constants of the step.  The floor products are rounded once
+// in the accumulation type (for f32x2: formed in FP64 and split), identically
+// in the forward and the adjoint's replay, so both take the same decisions.
+template <typename Acc>
+__device__ __forceinline__ StepConsts<Acc> step_consts(double theta_s, double theta_d,
+                                                       double var_init, double var_floor,
+                                                       double mask_floor) {
+  StepConsts<Acc> k;
+  if constexpr (is_f32x2<Acc>::value) {
+    k.theta_s = f32x2(theta_s);
+    k.theta_d = f32x2(theta_d);
+    k.var_init = f32x2(var_init);
+    k.ts_vf = f32x2(theta_s * var_floor);
+    k.td_mf = f32x2(theta_d * mask_floor);
+  } else {
+    k.theta_s = Acc(theta_s);
+    k.theta_d = Acc(theta_d);
+    k.var_init = Acc(var_init);
+    k.ts_vf = k.theta_s * Acc(var_floor);
+    k.td_mf = k.theta_d * Acc(mask_floor);
+  }
+  return k;
 }
 
 // blend u*a + w*b
@@ -98,6 +136,9 @@ struct StepRecord {
   Acc d;
   int idx;
   bool hitA, hitC, swap, fg;
+  // f32x2 only: the squared distances of the match tests and of the update
+  // (d*d), which the background test reuses
+  Acc qA, qC, V;
 };
 
 // True when the condition holds in any active lane of the wavefront.  Used to
@@ -105,12 +146,67 @@ struct StepRecord {
 // applies it under its own condition, so results do not depend on the wavefront.
 __device__ __forceinline__ bool any_lane(bool b) { return __builtin_amdgcn_ballot_w64(b) != 0; }
 
+// The step in compensated single precision.  The frames are floats, so x is
+// exact (x.lo = 0).  Same decisions and order as step_core() below, in the
+// algebraically equal forms that need fewer pair operations:
+//   m' = u*m + w*x = m + w*(x - m)     (u = 1 - w)
+//   d  = m' - x    = -u*(x - m)
+// with x - m taken from the match test, and the reset written as a select of
+// (x, var_init) so that it stays exact.
+__device__ __forceinline__ StepRecord<f32x2> step_core_x2(Model<f32x2>& s, const f32x2 xx,
+                                                          const StepConsts<f32x2>& k,
+                                                          const TableEntry<f32x2>* __restrict__ tbl) {
+  using namespace x2;
+  const float x = xx.hi;
+  const f32x2 dA = sub(x, s.mA);
+  const f32x2 qA = sqr(dA);
+  const f32x2 dC = sub(x, s.mC);
+  const f32x2 qC = sqr(dC);
+  const bool hitA = lt(qA, mul(k.theta_s, s.vA)) | lt(qA, k.ts_vf);
+  const bool hitC = lt(qC, mul(k.theta_s, s.vC)) | lt(qC, k.ts_vf);
+  const bool reset = !hitA && !hitC;
+
+  const int idx = hitA ? s.aA : (hitC ? s.aC : RESET_SLOT);
+  const f32x2 m = sel(hitA, s.mA, s.mC);
+  const f32x2 v = sel(hitA, s.vA, s.vC);
+  const f32x2 d0 = sel(hitA, dA, dC);
+  const TableEntry<f32x2> e = tbl[idx];
+
+  const f32x2 d = mul(f32x2(-e.u.hi, -e.u.lo), d0);  // 0 in the reset slot (u = 0)
+  const f32x2 V = sqr(d);
+  const f32x2 mn = sel(reset, f32x2(x), add(m, mul(e.w, d0)));
+  const f32x2 vn = sel(reset, k.var_init, add(mul(e.u, v), mul(e.w, V)));
+  const int an = e.next;
+
+  s.mA = sel(hitA, mn, s.mA);
+  s.vA = sel(hitA, vn, s.vA);
+  s.aA = hitA ? an : s.aA;
+  s.mC = sel(hitA, s.mC, mn);
+  s.vC = sel(hitA, s.vC, vn);
+  s.aC = hitA ? s.aC : an;
+
+  StepRecord<f32x2> r;
+  r.d = d;
+  r.idx = idx;
+  r.hitA = hitA;
+  r.hitC = hitC && !hitA;
+  r.swap = s.aC > s.aA;
+  r.fg = false;
+  r.qA = qA;
+  r.qC = qC;
+  r.V = V;
+  return r;
+}
+
 // Match tests, update of the matched model and the exchange decision (not yet
 // applied) for one frame of one pixel.  r.fg is left unset.
 template <typename Acc>
 __device__ __forceinline__ StepRecord<Acc> step_core(Model<Acc>& s, const Acc x,
                                                      const StepConsts<Acc>& k,
                                                      const TableEntry<Acc>* __restrict__ tbl) {
+  if constexpr (is_f32x2<Acc>::value) {
+    return step_core_x2(s, x, k, tbl);
+  } else {
   // q < theta*max(v, f)  <=>  q < theta*v  or  q < theta*f  for theta >= 0:
   // rounding is monotone, so round(theta*max(v,f)) = max(round(theta*v),
   // round(theta*f)); the floor products are per-launch constants.
@@ -154,6 +250,7 @@ __device__ __forceinline__ StepRecord<Acc> step_core(Model<Acc>& s, const Acc x,
   r.swap = s.aC > s.aA;
   r.fg = false;
   return r;
+  }
 }
 
 // The exchange: C older than A makes C the new A and resets C to (x, var_init, 1).
@@ -178,6 +275,24 @@ __device__ __forceinline__ bool fg_of(const Model<Acc>& s, const Acc x, const St
   return !((qd <= k.theta_d * ref) | (qd <= k.td_mf));
 }
 
+// The mask of the step given its record.  With f32x2 the squared distance
+// (mA - x)^2 after the step is one the step already formed: mA is the updated
+// model if A matched (d*d), the promoted C after an exchange (d*d if C
+// matched, else its untouched distance qC), and otherwise unchanged (qA).
+template <typename Acc, bool PRINTED>
+__device__ __forceinline__ bool fg_of(const Model<Acc>& s, const Acc x, const StepConsts<Acc>& k,
+                                      const StepRecord<Acc>& r) {
+  if constexpr (is_f32x2<Acc>::value) {
+    using namespace x2;
+    const f32x2 qd = sel(r.hitA != r.swap, r.V, sel(r.swap, r.qC, r.qA));
+    const f32x2 ref = PRINTED ? x : s.vA;
+    return !(le(qd, mul(k.theta_d, ref)) | le(qd, k.td_mf));
+  } else {
+    (void)r;
+    return fg_of<Acc, PRINTED>(s, x, k);
+  }
+}
+
 // One whole frame of one pixel (state updated in place).
 template <typename Acc, bool PRINTED>
 __device__ __forceinline__ StepRecord<Acc> step_rec(Model<Acc>& s, const Acc x,
@@ -185,7 +300,7 @@ __device__ __forceinline__ StepRecord<Acc> step_rec(Model<Acc>& s, const Acc x,
                                                     const TableEntry<Acc>* __restrict__ tbl) {
   StepRecord<Acc> r = step_core<Acc>(s, x, k, tbl);
   if (any_lane(r.swap)) apply_swap<Acc>(s, x, k, r.swap);
-  r.fg = fg_of<Acc, PRINTED>(s, x, k);
+  r.fg = fg_of<Acc, PRINTED>(s, x, k, r);
   return r;
 }
 
@@ -257,6 +372,10 @@ __device__ __forceinline__ float to_acc<bf16_t, float>(bf16_t v) {
 template <>
 __device__ __forceinline__ double to_acc<bf16_t, double>(bf16_t v) {
   return double(__uint_as_float(uint32_t(v.bits) << 16));
+}
+template <>
+__device__ __forceinline__ f32x2 to_acc<bf16_t, f32x2>(bf16_t v) {
+  return f32x2(__uint_as_float(uint32_t(v.bits) << 16));
 }
 
 // P consecutive elements, aligned to their total size so that the compiler

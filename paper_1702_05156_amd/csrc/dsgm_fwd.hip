@@ -42,6 +42,9 @@ hipError_t launch_init(const FwdArgs& a, int in_dtype, int acc, hipStream_t stre
   } else if (acc == 1) {
     if (in_dtype == 1) return launch_init_t<float, float>(a, stream);
     if (in_dtype == 2) return launch_init_t<bf16_t, float>(a, stream);
+  } else if (acc == 4) {
+    if (in_dtype == 1) return launch_init_t<float, f32x2>(a, stream);
+    if (in_dtype == 2) return launch_init_t<bf16_t, f32x2>(a, stream);
   }
   return hipErrorInvalidValue;
 }
@@ -58,6 +61,9 @@ hipError_t launch_forward(const FwdArgs& a, int in_dtype, int acc, int P, int fl
   } else if (acc == 2) {
     if (in_dtype == 1) return launch_fwd_f32_f64io32(a, P, flags, block, stream);
     if (in_dtype == 2) return launch_fwd_bf16_f64io32(a, P, flags, block, stream);
+  } else if (acc == 4) {
+    if (in_dtype == 1) return launch_fwd_f32_f32x2(a, P, flags, block, stream);
+    if (in_dtype == 2) return launch_fwd_bf16_f32x2(a, P, flags, block, stream);
   }
   return hipErrorInvalidValue;
 }

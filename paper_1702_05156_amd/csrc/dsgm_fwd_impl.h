@@ -74,13 +74,7 @@ template <typename Acc>
 __device__ __forceinline__ StepConsts<Acc> make_consts(double theta_s, double theta_d,
                                                       double var_init, double var_floor,
                                                       double mask_floor) {
-  StepConsts<Acc> k;
-  k.theta_s = Acc(theta_s);
-  k.theta_d = Acc(theta_d);
-  k.var_init = Acc(var_init);
-  k.ts_vf = k.theta_s * Acc(var_floor);
-  k.td_mf = k.theta_d * Acc(mask_floor);
-  return k;
+  return step_consts<Acc>(theta_s, theta_d, var_init, var_floor, mask_floor);
 }
 
 template <typename Acc>
@@ -197,7 +191,7 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
     }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      r[q].fg = fg_of<Acc, PRINTED>(s[q], xs[q], k);
+      r[q].fg = fg_of<Acc, PRINTED>(s[q], xs[q], k, r[q]);
       mk.v[q] = r[q].fg ? uint8_t(255) : uint8_t(0);
       if (BG) bgv.v[q] = Io(s[q].mA);  // rounded once when Io is narrower
       if (CODES) cd.v[q] = uint8_t(code_of<Acc>(r[q]));
@@ -424,6 +418,14 @@ const void* batched_symbol_t(int P, int flags) {
 }
 
 }  // namespace fwd
+
+// The single-instance forward only (no batched kernel), for state types the
+// batched launch does not take.
+#define DSGM_FWD_INSTANTIATE_SINGLE(IN, ACC, IO, NAME)                                     \
+  hipError_t launch_fwd_##NAME(const FwdArgs& a, int P, int flags, int block,              \
+                               hipStream_t stream) {                                       \
+    return fwd::launch_fwd_t<IN, ACC, IO>(a, P, flags, block, stream);                     \
+  }
 
 // One translation unit per (frame type, accumulation type) instantiates these.
 #define DSGM_FWD_INSTANTIATE(IN, ACC, IO, NAME)                                            \

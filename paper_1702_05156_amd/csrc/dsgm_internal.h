@@ -100,7 +100,7 @@ hipError_t launch_batched(const BatchArgs& a, int in_dtype, int acc, int P, int 
                           hipStream_t stream);
 
 // in_dtype: 0 f64, 1 f32, 2 bf16; acc: 0 f64, 1 f32, 2 f64 state with f32 bg and
-// gradients; P in {1, 2, 4}; flags FWD_*
+// gradients, 4 f32x2 state with f32 bg and gradients; P in {1, 2, 4}; flags FWD_*
 hipError_t launch_forward(const FwdArgs& a, int in_dtype, int acc, int P, int flags, int block,
                           hipStream_t stream);
 
@@ -117,6 +117,8 @@ DSGM_FWD_DECLARE(bf16_f32)
 DSGM_FWD_DECLARE(f32_f64io32)
 DSGM_FWD_DECLARE(bf16_f64io32)
 #undef DSGM_FWD_DECLARE
+hipError_t launch_fwd_f32_f32x2(const FwdArgs& a, int P, int flags, int block, hipStream_t stream);
+hipError_t launch_fwd_bf16_f32x2(const FwdArgs& a, int P, int flags, int block, hipStream_t stream);
 
 // state = (x, var_init, 1) for both models from frame 0 (uses frames, the
 // state planes, H, W, row_stride, var_init)

@@ -23,19 +23,35 @@ DSGM_OK = 0
 STATUS = {0: "DSGM_OK", -1: "DSGM_E_ARG", -2: "DSGM_E_SHAPE", -3: "DSGM_E_DTYPE",
           -4: "DSGM_E_ALIGN", -5: "DSGM_E_WORKSPACE", -6: "DSGM_E_HIP", -7: "DSGM_E_UNSUPPORTED"}
 IN_F64, IN_F32, IN_BF16, IN_U8 = 0, 1, 2, 3
-ACC_F64, ACC_F32, ACC_F64_IO32, ACC_U8 = 0, 1, 2, 3
+ACC_F64, ACC_F32, ACC_F64_IO32, ACC_U8, ACC_F32X2 = 0, 1, 2, 3, 4
 WEIGHT_EQ, WEIGHT_APPENDIX = 0, 1
 MASK_VARIANCE, MASK_PRINTED = 0, 1
 CODE_HIT_A, CODE_HIT_C, CODE_RESET, CODE_SWAP, CODE_FG = 1, 2, 4, 8, 16
 
 _IN_DTYPES = {torch.float64: IN_F64, torch.float32: IN_F32, torch.bfloat16: IN_BF16,
               torch.uint8: IN_U8}
-_ACC_DTYPES = {torch.float64: ACC_F64, torch.float32: ACC_F32, torch.uint8: ACC_U8}
+# F32X2 state planes are complex64 tensors: the (hi, lo) float pairs of the
+# library's layout, hi in the real part and lo in the imaginary part
+_ACC_DTYPES = {torch.float64: ACC_F64, torch.float32: ACC_F32, torch.uint8: ACC_U8,
+               torch.complex64: ACC_F32X2}
 # dtype of bg and of the gradient arrays, and of the model state, per dsgm_acc
 ACC_TORCH = {ACC_F64: torch.float64, ACC_F32: torch.float32, ACC_F64_IO32: torch.float32,
-             ACC_U8: torch.uint8}
+             ACC_U8: torch.uint8, ACC_F32X2: torch.float32}
 STATE_TORCH = {ACC_F64: torch.float64, ACC_F32: torch.float32, ACC_F64_IO32: torch.float64,
-               ACC_U8: torch.uint8}
+               ACC_U8: torch.uint8, ACC_F32X2: torch.complex64}
+
+
+def x2_from_f64(t: torch.Tensor) -> torch.Tensor:
+    """The nearest (hi, lo) float pairs of a float64 tensor, as complex64:
+    hi = fl32(t), lo = fl32(t - hi); hi + lo is exact in float64."""
+    hi = t.to(torch.float32)
+    lo = (t - hi.double()).to(torch.float32)
+    return torch.complex(hi, lo)
+
+
+def x2_to_f64(t: torch.Tensor) -> torch.Tensor:
+    """hi + lo of complex64 pairs, in float64 (exact)."""
+    return t.real.double() + t.imag.double()
 
 
 class DSGMError(RuntimeError):
@@ -595,6 +611,9 @@ class DSGMFunction(torch.autograd.Function):
         st = State(mean_a.detach().clone(), var_a.detach().clone(), mean_c.detach().clone(),
                    var_c.detach().clone(), age_a.detach().clone(), age_c.detach().clone())
         acc = _resolve_acc(st, acc)
+        if acc == ACC_F32X2:
+            raise NotImplementedError("DSGMFunction: F32X2 state has no autograd form; call "
+                                      "forward() and backward() directly")
         out = forward(frames.detach(), st, p, bg=True, ckpt_every=ckpt_every, acc=acc)
         ctx.save_for_backward(frames, out["ckpt"])
         ctx.params, ctx.K, ctx.acc = p, ckpt_every, acc

@@ -177,6 +177,32 @@ def test_backward_noalloc_validation():
     assert _bwd_na(shape=(1, 3, 2796203, 2796203, 3 * 2796203)) == -5
 
 
+def test_f32x2_validation():
+    """The compensated pair state: F32 or BF16 frames, 8-byte values (the
+    checkpoint size of FP64 state), dsgm_forward/dsgm_backward only."""
+    assert _fwd(in_dtype=1, acc=4, shape=(0, 8, 8, 8, 64)) == 0
+    assert _fwd(in_dtype=0, acc=4) == -3                 # FP64 frames
+    assert _fwd(in_dtype=3, acc=4) == -3                 # 8-bit frames
+    assert _fwd(in_dtype=1, acc=4, bg=FAKE + 2) == -4    # FP32 bg alignment
+    assert _bwd(in_dtype=0, acc=4) == -3
+    assert _bwd(in_dtype=1, acc=4, ws_bytes=16) == -5
+    sh = dsgm.Shape(100, 3, 5, 5, 15)
+    assert lib.dsgm_ckpt_bytes(sh, 4, 32) == lib.dsgm_ckpt_bytes(sh, 0, 32)
+    assert lib.dsgm_workspace_bytes(sh, 4) == lib.dsgm_workspace_bytes(sh, 0)
+    one = (dsgm.Instance * 1)(_inst())
+    assert lib.dsgm_batch_plan_bytes(one, 1, 1, 4) == 0
+    assert b"F32X2" in lib.dsgm_last_error()
+    p = dsgm.dsgm_params_default(2.0)
+    st = _state()
+    f = dsgm.gauss_filter(5, 1.0, True)
+    rc = lib.dsgm_forward_filtered(FAKE, 1, dsgm.Shape(2, 8, 8, 8, 64), 4, ctypes.byref(p),
+                                   ctypes.byref(f), ctypes.byref(st), FAKE, None, None, None, None)
+    assert rc == -3
+    rc = lib.dsgm_forward_grid(FAKE, 1, dsgm.Shape(2, 8, 8, 8, 64), 4, ctypes.byref(p), 4,
+                               ctypes.byref(st), FAKE, None, None, None)
+    assert rc == -3
+
+
 def _inst(T=4, H=8, W=8, ptr=FAKE, bg=None):
     return dsgm.Instance(dsgm.Shape(T, H, W, W, H * W), ptr, _state(ptr), ptr, bg)
 
