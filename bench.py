@@ -652,7 +652,9 @@ def leg_largest(args, dsgm, sdev, torch):
     # the band run alone is the full run's arithmetic for those pixels): the
     # FP32 bg and gradients must be the FP64 values rounded once
     R = 64
-    sb = dsgm.State(*(t[:R].contiguous() for t in st0.planes()))
+    # copies (a row slice of a dense plane is itself dense, and the forward
+    # updates the state it is given in place)
+    sb = dsgm.State(*(t[:R].clone() for t in st0.planes()))
     fb = fr[:, :R].contiguous()  # dense, so the outputs dsgm.forward allocates are too
     ob = dsgm.forward(fb, sb, p, bg=True, ckpt_every=K)
     rb = dsgm.backward(fb, p, ob["ckpt"], K, dsgm.ACC_F64, gbg[:, :R].double(),
@@ -666,9 +668,65 @@ def leg_largest(args, dsgm, sdev, torch):
            "grad_frames_equal_fp64_rounded_once": bool(torch.equal(gx[:, :R], gx64.float())),
            "max_rel_err_bg": rel(bg[:, :R], bg64),
            "max_rel_err_grad_frames": rel(gx[:, :R], gx64)}
-    del sb, fb, ob, rb, bg64, gx64
+    gvi_io32 = float(gvi.item())
+    del sb, ob, rb, bg64, gx64
+    # the same instance in compensated single precision (F32X2: (hi, lo) float
+    # pairs, FP32 instruction rates), from the pairs nearest to the FP64 start,
+    # timed on the same buffers (the pair state has the FP64 state's size)
+    x2 = dsgm.ACC_F32X2
+    sx = dsgm.State(*(dsgm.x2_from_f64(t) if t.is_floating_point() else t.clone()
+                      for t in st0.planes()))
+    sx0 = sx.clone()
+    msf2, kf2 = timed(lambda: dsgm.dsgm_forward(fr, sx, p, masks, bg, ck, K, acc=x2), steps, 1,
+                      stream)
+    for a, b in zip(sx.planes(), sx0.planes()):
+        a.copy_(b)
+    dsgm.dsgm_forward(fr, sx, p, masks, bg, ck, K, acc=x2)
+    msb2, kb2 = timed(lambda: dsgm.dsgm_backward(fr, p, ck, K, x2, gbg, gst, gx, gs0, gvi, ws),
+                      steps, 1, stream)
+    gvi_x2 = float(gvi.item())
+    # the band again in FP64 (GPU FP64 path = the oracle's arithmetic) from the
+    # pair values, against the pair run's outputs on that band
+    sb = dsgm.State(*(dsgm.x2_to_f64(t[:R]) if t.is_complex() else t[:R].clone()
+                      for t in sx0.planes()))
+    ob = dsgm.forward(fb, sb, p, bg=True, codes=True, ckpt_every=K)
+    sxb = dsgm.State(*(t[:R].clone() for t in sx0.planes()))
+    cb = torch.empty_like(ob["codes"])
+    dsgm.dsgm_forward(fb, sxb, p, torch.empty_like(ob["masks"]), codes=cb)
+    rb = dsgm.backward(fb, p, ob["ckpt"], K, dsgm.ACC_F64, gbg[:, :R].double(),
+                       tuple(g[:R].double() for g in gst))
+    torch.cuda.synchronize()
+    def beyond(a, r):
+        """largest |a - r| beyond half an FP32 ulp of r (<= 0: rounded once)"""
+        f = r.float().abs()
+        half_ulp = 0.5 * (torch.nextafter(f, torch.full_like(f, float("inf"))).double() - f.double())
+        return float(((a.double() - r).abs() - half_ulp).max())
+    fin = {k: float((dsgm.x2_to_f64(getattr(sx, k)[:R]) - getattr(sb, k)).abs().max())
+           for k in ("mean_a", "var_a", "mean_c", "var_c")}
+    err_x2 = {"band": f"rows 0-{R - 1}, all {T} frames, against the FP64 path from the same values",
+              "decision_elements_differing": int((cb != ob["codes"]).sum().item()),
+              "masks_equal": bool(torch.equal(masks[:, :R], ob["masks"])),
+              "max_abs_err_final_state": max(fin.values()),
+              "bg_beyond_half_ulp_of_fp64": beyond(bg[:, :R], ob["bg"]),
+              "grad_frames_beyond_half_ulp_of_fp64": beyond(gx[:, :R], rb["grad_frames"]),
+              "max_rel_err_grad_frames": rel(gx[:, :R], rb["grad_frames"])}
+    del sb, fb, ob, rb, sxb, cb, sx, sx0
     elems, px = T * H * W, H * W
     ck_slots = (T + K - 1) // K
+    out_x2 = {"workload": "the same instance with F32X2 state (compensated FP32 pairs), "
+                          "fp32 bg/gradients",
+              "forward": {"elements_per_s": round(elems / (msf2 * 1e-3), 1),
+                          "ms_per_step": round(msf2, 3),
+                          "roofline": roof(elems * 9 + px * 68, float(sum(kf2) / len(kf2)), elems,
+                                           OPS_STEP, fp32=True)},
+              "backward": {"elements_per_s": round(elems / (msb2 * 1e-3), 1),
+                           "ms_per_step": round(msb2, 3),
+                           "roofline": roof(elems * 12 + px * 40, float(sum(kb2) / len(kb2)), elems,
+                                            OPS_ADJOINT, fp32=True)},
+              "grad_var_init": gvi_x2,
+              "time_ratio_over_f64_io32": {"forward": round(msf2 / msf, 3),
+                                           "backward": round(msb2 / msb, 3)},
+              "error_vs_fp64": err_x2}
     out = {"workload": "2160x3840x1344 fp32 frames, fp64 state, fp32 bg/gradients, K=32, seed 4",
            "resident_bytes": int(resident),
            "forward": {"elements_per_s": round(elems / (msf * 1e-3), 1), "ms_per_step": round(msf, 3),
@@ -677,8 +735,9 @@ def leg_largest(args, dsgm, sdev, torch):
            "backward": {"elements_per_s": round(elems / (msb * 1e-3), 1), "ms_per_step": round(msb, 3),
                         "roofline": roof(elems * 12 + px * 40, float(sum(kb) / len(kb)), elems, OPS_ADJOINT),
                         "checkpoint_bytes_read": ck_slots * px * 34},
-           "grad_var_init": float(gvi.item()),
-           "error_vs_fp64": err}
+           "grad_var_init": gvi_io32,
+           "error_vs_fp64": err,
+           "f32x2": out_x2}
     del fr, st, st0, masks, bg, ck, gbg, gst, gx, gs0, gvi, ws
     torch.cuda.empty_cache()
     return out
@@ -715,8 +774,20 @@ def _batch_items(shapes, idx, dsgm, sdev, torch, frames_dtype, state_dtype, st0)
         cp = lambda t: t.to(dtype=state_dtype, copy=True)  # never the initial state itself
         st = dsgm.State(cp(s.mean_a), cp(s.var_a), cp(s.mean_c), cp(s.var_c), s.age_a.clone(),
                         s.age_c.clone())
-        items.append((fr, st, torch.empty((T, H, W), dtype=torch.uint8, device="cuda"), None))
+        # every instance counts its foreground pixels per frame (the batched
+        # launch's reduction: exact integer sums, one atomic per wavefront and frame)
+        items.append((fr, st, torch.empty((T, H, W), dtype=torch.uint8, device="cuda"), None,
+                      torch.empty((T,), dtype=torch.int32, device="cuda")))
     return items
+
+
+def _counts_exact(items, torch):
+    """every instance's counters equal the 255s of its masks, frame by frame"""
+    for _, _, m, _, c in items:
+        T = m.shape[0]
+        if not torch.equal(c, (m.view(T, -1) == 255).sum(dim=1).to(torch.int32)):
+            return False
+    return True
 
 
 def leg_batched(args, dsgm, sdev, torch):
@@ -753,12 +824,14 @@ def leg_batched(args, dsgm, sdev, torch):
     alg = elems * 3 + px * 36
     n_items, grid = int(batch.plan.n_items), int(batch.plan.grid)
     # one pass from the initial state for the accuracy comparison
-    for (_, st, _, _), s0 in zip(items, st0):
+    for (_, st, _, _, _), s0 in zip(items, st0):
         for a, b in zip(st.planes(), s0.planes()):
             a.copy_(b)
     batch.run(p)
     torch.cuda.synchronize()
-    masks_mixed = [m for _, _, m, _ in items]
+    counts_ok = _counts_exact(items, torch)
+    fg_total = sum(int(c.sum().item()) for *_, c in items)
+    masks_mixed = [m for _, _, m, _, _ in items]
     del items, batch, g
     torch.cuda.empty_cache()
 
@@ -781,7 +854,8 @@ def leg_batched(args, dsgm, sdev, torch):
         b64 = dsgm.Batch(it)
         b64.run(p)
         torch.cuda.synchronize()
-        for i, (_, _, m, _) in zip(idx, it):
+        counts_ok = counts_ok and _counts_exact(it, torch)
+        for i, (_, _, m, _, _) in zip(idx, it):
             d = m != masks_mixed[i]
             diff_elems += int(d.sum().item())
             diff_px += int(d.any(dim=0).sum().item())
@@ -793,7 +867,9 @@ def leg_batched(args, dsgm, sdev, torch):
     del masks_mixed, st0
     torch.cuda.empty_cache()
     out = {"workload": "512 instances, log-uniform 1x..256x of 320x240x32, bf16 frames, fp32 state, "
-                       "masks only, seed 3",
+                       "masks and per-frame foreground counts, seed 3",
+           "fg_counts_equal_mask_sums": counts_ok,
+           "foreground_fraction": fg_total / elems,
            "instances": len(shapes), "total_elements": int(elems), "work_items": n_items,
            "persistent_workgroups": grid,
            "autotuned_pixels_per_lane": tuned["vector"],

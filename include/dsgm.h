@@ -336,7 +336,11 @@ typedef struct {
   const void* frames;
   dsgm_state state;
   uint8_t* masks;
-  void* bg; /* NULL: no bg output */
+  void* bg;             /* NULL: no bg output */
+  uint32_t* fg_counts;  /* NULL, or T counters (device, 4-byte aligned): after the
+                           launch, entry t holds the number of foreground pixels of
+                           frame t (mask 255), an exact integer sum; each launch
+                           clears them first */
 } dsgm_instance;
 
 /* host-side handle of a planned batch (plain data, owned by the caller) */
@@ -349,6 +353,7 @@ typedef struct {
   int32_t vector;         /* pixels per lane, common to all instances         */
   int32_t grid;           /* persistent workgroups (device-resident count)    */
   int32_t has_bg;
+  int32_t has_counts;     /* some instance has foreground counters            */
 } dsgm_batch_plan;
 
 /* bytes of the device plan buffer for these instances (0 on bad arguments) */
@@ -373,11 +378,15 @@ int dsgm_plan_batched(const dsgm_instance* instances /* host */, int32_t n, dsgm
 /*
  * Run every instance of a plan through all of its frames (the per-instance
  * results are those of dsgm_forward on that instance alone): one small kernel
- * resets the plan's work counter, then one persistent kernel whose wavefronts
- * take items from it until none are left.  Enqueues exactly these two kernels
- * and nothing else (no allocation, no copy, no synchronization), so the call
- * can be captured into a HIP graph and replayed.  Launches of one plan must
- * not overlap (they share the counter).
+ * resets the plan's work counter, a second clears the foreground counters
+ * when some instance has them (plan.has_counts), then one persistent kernel
+ * whose wavefronts take items from it until none are left; each wavefront adds
+ * its foreground pixels of each frame to the instance's counter with one
+ * integer atomic, so the counts are exact and do not depend on the schedule.
+ * Enqueues exactly these kernels and nothing else (no allocation, no copy, no
+ * memset, no synchronization), so the call can be captured into a HIP graph
+ * and replayed.  Launches of one plan must not overlap (they share the
+ * counters).
  */
 int dsgm_forward_batched(const dsgm_batch_plan* plan /* host */, const dsgm_params* params /* host */,
                          hipStream_t stream);

@@ -189,8 +189,8 @@ int64_t pad_to(int64_t b, int64_t a) { return (b + a - 1) / a * a; }
 
 struct PlanLayout {
   int P = 4;
-  int64_t n_items = 0, total = 0, inst_off = 0, items_off = 0, bytes = 0;
-  bool bg = false;
+  int64_t n_items = 0, total = 0, inst_off = 0, items_off = 0, stripes_off = 0, bytes = 0;
+  bool bg = false, counts = false;
 };
 
 // validate the instances and lay out the device plan; no HIP call
@@ -201,6 +201,7 @@ int plan_layout(const dsgm_instance* inst, int32_t n, int in_dtype, int acc, Pla
   const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
   int P = 4;
   L->bg = false;
+  L->counts = false;
   for (int32_t i = 0; i < n; ++i) {
     const dsgm_instance& I = inst[i];
     if ((rc = check_shape(I.shape, ie > oe ? ie : oe)))
@@ -212,31 +213,34 @@ int plan_layout(const dsgm_instance* inst, int32_t n, int in_dtype, int acc, Pla
       return fail(DSGM_E_ARG, "instance %d: a required pointer is NULL", i);
     const void* ptrs[10] = {I.frames, I.masks, I.bg, I.state.mean_a, I.state.var_a,
                             I.state.mean_c, I.state.var_c, I.state.age_a, I.state.age_c,
-                            nullptr};
-    const size_t elem[10] = {ie, 1, oe, ae, ae, ae, ae, 1, 1, 1};
-    for (int k = 0; k < 9; ++k)
+                            I.fg_counts};
+    const size_t elem[10] = {ie, 1, oe, ae, ae, ae, ae, 1, 1, 4};
+    for (int k = 0; k < 10; ++k)
       if (ptrs[k] && !aligned(ptrs[k], elem[k]))
         return fail(DSGM_E_ALIGN, "instance %d: pointer %d not aligned to %zu bytes", i, k, elem[k]);
-    P = std::min(P, pick_vector(I.shape, ptrs, elem, 9));
+    P = std::min(P, pick_vector(I.shape, ptrs, elem, 9));  // the counters do not limit P
     if (I.bg) L->bg = true;
+    if (I.fg_counts) L->counts = true;
   }
   const int widest = P;
   P = std::min(P, preferred_vector(in_dtype, acc));
   const int vo = g_vector_override.load(std::memory_order_relaxed);
   if (vo && widest % vo == 0) P = vo;
-  int64_t items = 0, total = 0;
+  int64_t items = 0, total = 0, stripes = 0;
   for (int32_t i = 0; i < n; ++i) {
     const dsgm_shape& s = inst[i].shape;
     if (s.H * s.W == 0 || s.T == 0) continue;
     items += (s.H * (s.W / P) + 63) / 64;
     total += s.T * s.H * s.W;
+    if (inst[i].fg_counts) stripes += pad_to(s.T * dsgm::COUNT_STRIPES * 4, 256);
   }
   L->P = P;
   L->n_items = items;
   L->total = total;
   L->inst_off = kPlanHeader;
   L->items_off = kPlanHeader + pad_to(int64_t(n) * int64_t(sizeof(dsgm::BatchInst)), 256);
-  L->bytes = L->items_off + pad_to(items * int64_t(sizeof(dsgm::BatchItem)), 256);
+  L->stripes_off = L->items_off + pad_to(items * int64_t(sizeof(dsgm::BatchItem)), 256);
+  L->bytes = L->stripes_off + stripes;
   return DSGM_OK;
 }
 
@@ -1067,12 +1071,20 @@ int dsgm_plan_batched(const dsgm_instance* instances, int32_t n, dsgm_in_dtype i
   auto* desc = reinterpret_cast<dsgm::BatchInst*>(host.data() + L.inst_off);
   auto* items = reinterpret_cast<dsgm::BatchItem*>(host.data() + L.items_off);
   int64_t k = 0;
+  int64_t stripe_at = L.stripes_off;
   for (int32_t i = 0; i < n; ++i) {
     const dsgm_instance& I = instances[i];
     dsgm::BatchInst& d = desc[i];
     d.frames = I.frames;
     d.masks = I.masks;
     d.bg = I.bg;
+    // counters of an instance with no work are never cleared: none are kept
+    d.fg_counts = (I.shape.H * I.shape.W == 0 || I.shape.T == 0) ? nullptr : I.fg_counts;
+    d.stripes = nullptr;
+    if (d.fg_counts) {
+      d.stripes = reinterpret_cast<uint32_t*>(static_cast<char*>(plan_buffer) + stripe_at);
+      stripe_at += pad_to(I.shape.T * dsgm::COUNT_STRIPES * 4, 256);
+    }
     d.state[0] = I.state.mean_a;
     d.state[1] = I.state.var_a;
     d.state[2] = I.state.mean_c;
@@ -1118,6 +1130,7 @@ int dsgm_plan_batched(const dsgm_instance* instances, int32_t n, dsgm_in_dtype i
   plan->vector = P;
   plan->grid = std::max(1, per_cu) * std::max(1, ncu);
   plan->has_bg = L.bg ? 1 : 0;
+  plan->has_counts = L.counts ? 1 : 0;
   return ok();
 }
 
@@ -1135,6 +1148,7 @@ int dsgm_forward_batched(const dsgm_batch_plan* plan, const dsgm_params* params,
   memset(&a, 0, sizeof(a));
   a.counter = reinterpret_cast<unsigned long long*>(base);
   a.inst = reinterpret_cast<const dsgm::BatchInst*>(base + kPlanHeader);
+  a.n_inst = plan->n_instances;
   a.items = reinterpret_cast<const dsgm::BatchItem*>(
       base + kPlanHeader + pad_to(int64_t(plan->n_instances) * int64_t(sizeof(dsgm::BatchInst)), 256));
   a.n_items = plan->n_items;
@@ -1149,7 +1163,7 @@ int dsgm_forward_batched(const dsgm_batch_plan* plan, const dsgm_params* params,
   const int flags = (plan->has_bg ? dsgm::FWD_BG : 0) |
                     (params->mask_rule == DSGM_MASK_PRINTED ? dsgm::FWD_PRINTED : 0);
   hipError_t e = dsgm::launch_batched(a, plan->in_dtype, plan->acc, plan->vector, flags,
-                                      plan->grid, stream);
+                                      plan->grid, plan->has_counts != 0, stream);
   if (e != hipSuccess) return hip_fail(e, "dsgm_forward_batched launch");
   return ok();
 }

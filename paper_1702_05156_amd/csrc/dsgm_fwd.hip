@@ -11,6 +11,28 @@ __global__ void counter_reset(unsigned long long* counter) {
   if (threadIdx.x == 0) *counter = 0ull;
 }
 
+// clears the count stripes of every instance that has foreground counters
+// (one block per instance); a kernel rather than a memset so that the launch
+// sequence can be captured into a graph and replayed
+__global__ void __launch_bounds__(256) counts_reset(const BatchInst* inst) {
+  const BatchInst& I = inst[blockIdx.x];
+  if (I.fg_counts == nullptr) return;
+  const int64_t n = I.T * COUNT_STRIPES;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) I.stripes[i] = 0u;
+}
+
+// adds each instance's stripes into its counters (one block per instance;
+// integer sums, exact in any order)
+__global__ void __launch_bounds__(256) counts_sum(const BatchInst* inst) {
+  const BatchInst& I = inst[blockIdx.x];
+  if (I.fg_counts == nullptr) return;
+  for (int64_t t = threadIdx.x; t < I.T; t += blockDim.x) {
+    uint32_t c = 0u;
+    for (int s = 0; s < COUNT_STRIPES; ++s) c += I.stripes[int64_t(s) * I.T + t];
+    I.fg_counts[t] = c;
+  }
+}
+
 template <typename In, typename Acc>
 __global__ void __launch_bounds__(256) init_kernel(const FwdArgs a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -84,15 +106,23 @@ const void* batched_kernel_symbol(int in_dtype, int acc, int P, int flags) {
 }
 
 hipError_t launch_batched(const BatchArgs& a, int in_dtype, int acc, int P, int flags, int grid,
-                          hipStream_t stream) {
+                          bool counts, hipStream_t stream) {
   const void* fn = batched_kernel_symbol(in_dtype, acc, P, flags);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(counter_reset, dim3(1), dim3(64), 0, stream, a.counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (counts) {
+    hipLaunchKernelGGL(counts_reset, dim3(uint32_t(a.n_inst)), dim3(256), 0, stream, a.inst);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   BatchArgs args = a;
   void* kargs[] = {&args};
-  return hipLaunchKernel(fn, dim3(uint32_t(grid)), dim3(256), kargs, 0, stream);
+  e = hipLaunchKernel(fn, dim3(uint32_t(grid)), dim3(256), kargs, 0, stream);
+  if (e != hipSuccess || !counts) return e;
+  hipLaunchKernelGGL(counts_sum, dim3(uint32_t(a.n_inst)), dim3(256), 0, stream, a.inst);
+  return hipGetLastError();
 }
 
 }  // namespace dsgm

@@ -85,8 +85,10 @@ __device__ __forceinline__ void fill_table(TableEntry<Acc>* tbl, int weight_rule
   __syncthreads();
 }
 
-// Compile-time variants of the forward kernels.
-enum : int { F_BG = FWD_BG, F_CODES = FWD_CODES, F_CKPT = FWD_CKPT, F_PRINTED = FWD_PRINTED };
+// Compile-time variants of the forward kernels.  F_COUNT (batched kernel
+// only) adds the per-frame foreground counts of instances that have counters.
+enum : int { F_BG = FWD_BG, F_CODES = FWD_CODES, F_CKPT = FWD_CKPT, F_PRINTED = FWD_PRINTED,
+             F_COUNT = 16 };
 
 // Everything one lane needs to run its pixel group through T frames.
 struct GroupJob {
@@ -96,6 +98,7 @@ struct GroupJob {
   char* codes;         // used with F_CODES
   char* state[6];      // the six planes (element 0)
   char* ckpt;          // used with F_CKPT: checkpoint slot 0
+  uint32_t* counts;    // used with F_COUNT: T foreground counters (this item's stripe)
   int64_t ckpt_every, ckpt_slot_bytes, ckpt_fplane, ckpt_aplane;
   int64_t T, frame_stride;
   uint32_t foff;       // element offset of the group within a frame (< 2^31)
@@ -131,6 +134,7 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
   constexpr bool CODES = (FLAGS & F_CODES) != 0;
   constexpr bool CKPT = (FLAGS & F_CKPT) != 0;
   constexpr bool PRINTED = (FLAGS & F_PRINTED) != 0;
+  constexpr bool COUNT = (FLAGS & F_COUNT) != 0;
   Model<Acc> s[P];
   {
     const int64_t o = j.soff * int64_t(sizeof(Acc));
@@ -196,6 +200,15 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
       if (BG) bgv.v[q] = Io(s[q].mA);  // rounded once when Io is narrower
       if (CODES) cd.v[q] = uint8_t(code_of<Acc>(r[q]));
     }
+    if (COUNT && j.counts != nullptr) {  // uniform: the item's instance has counters
+      // the wavefront's foreground pixels of this frame: one ballot per pixel
+      // of the lane group, summed in scalar registers, one integer atomic
+      // (exact, order-free) from the first lane; every caller has lane 0 active
+      uint32_t n = 0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) n += uint32_t(__builtin_popcountll(__builtin_amdgcn_ballot_w64(r[q].fg)));
+      if ((threadIdx.x & 63) == 0 && n != 0) atomicAdd(j.counts + t, n);
+    }
     const int64_t o = t * fs;
     st_stream<uint8_t, P>(reinterpret_cast<uint8_t*>(j.masks + o + j.foff), mk);
     if (BG) st_stream<Io, P>(reinterpret_cast<Io*>(j.bg + o * int64_t(sizeof(Io)) + off_io), bgv);
@@ -256,6 +269,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const FwdArgs a) {
   j.state[4] = reinterpret_cast<char*>(a.age_a);
   j.state[5] = reinterpret_cast<char*>(a.age_c);
   j.ckpt = static_cast<char*>(a.ckpt);
+  j.counts = nullptr;
   j.ckpt_every = a.ckpt_every;
   j.ckpt_slot_bytes = a.ckpt_slot_bytes;
   j.ckpt_fplane = a.ckpt_fplane;
@@ -292,6 +306,22 @@ constexpr int batched_waves() {
   return (sizeof(In) == 2 && sizeof(Acc) == 4 && P == 4 && (FLAGS & F_BG) == 0) ? 5 : 1;
 }
 
+// One work item of the batched kernel; a batch with bg outputs may hold
+// instances without.
+template <typename In, typename Acc, typename Io, int P, int U, int FLAGS>
+__device__ __forceinline__ void run_item(const GroupJob& j, const BatchInst& I,
+                                         const StepConsts<Acc>& k,
+                                         const TableEntry<Acc>* __restrict__ tbl) {
+  if constexpr ((FLAGS & F_BG) != 0) {
+    if (I.bg != nullptr)
+      run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl);
+    else
+      run_group<In, Acc, Io, P, U, FLAGS & ~F_BG>(j, k, tbl);
+  } else {
+    run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl);
+  }
+}
+
 // FLAGS may only hold F_BG and F_PRINTED (no codes, no checkpoints)
 template <typename In, typename Acc, typename Io, int P, int U, int FLAGS>
 __global__ void __launch_bounds__(256)
@@ -325,20 +355,16 @@ __global__ void __launch_bounds__(256)
       j.codes = nullptr;
       for (int q = 0; q < 6; ++q) j.state[q] = static_cast<char*>(I.state[q]);
       j.ckpt = nullptr;
+      j.counts = I.fg_counts ? I.stripes + int64_t(item % COUNT_STRIPES) * I.T : nullptr;
       j.ckpt_every = 1;
       j.ckpt_slot_bytes = j.ckpt_fplane = j.ckpt_aplane = 0;
       j.T = I.T;
       j.frame_stride = I.frame_stride;
       j.foff = uint32_t(h * I.row_stride + w0);
       j.soff = h * I.W + w0;
-      if constexpr ((FLAGS & F_BG) != 0) {
-        if (I.bg != nullptr)  // a batch with bg outputs may hold instances without
-          run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl);
-        else
-          run_group<In, Acc, Io, P, U, FLAGS & ~F_BG>(j, k, tbl);
-      } else {
-        run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl);
-      }
+      // one body for instances with and without foreground counters (a
+      // uniform run-time test per frame), so the kernel's code stays one copy
+      run_item<In, Acc, Io, P, U, FLAGS | F_COUNT>(j, I, k, tbl);
     }
   }
 }

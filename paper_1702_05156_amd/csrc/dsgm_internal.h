@@ -63,10 +63,18 @@ hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* ou
                          hipStream_t stream);
 
 // Batched forward: device-side descriptors written by the host planner.
+// The foreground counts of an instance are accumulated in COUNT_STRIPES
+// copies (stripe = work item mod COUNT_STRIPES, each T counters) so that the
+// wavefronts working on one instance at the same time add to different
+// addresses; a last small kernel adds the stripes into the caller's counters.
+constexpr int COUNT_STRIPES = 256;
+
 struct BatchInst {
   const void* frames;
   uint8_t* masks;
-  void* bg;  // NULL: no bg for this instance
+  void* bg;             // NULL: no bg for this instance
+  uint32_t* fg_counts;  // NULL: no foreground counts for this instance
+  uint32_t* stripes;    // with fg_counts: COUNT_STRIPES x T counters in the plan buffer
   void* state[6];
   int64_t T, H, W, row_stride, frame_stride, groups_per_row;
 };
@@ -79,12 +87,13 @@ struct BatchItem {
   int32_t pad;
 };
 
-static_assert(sizeof(BatchInst) == 120, "plan layout: instance descriptor size");
+static_assert(sizeof(BatchInst) == 136, "plan layout: instance descriptor size");
 static_assert(sizeof(BatchItem) == 16, "plan layout: item size");
 
 struct BatchArgs {
   unsigned long long* counter;  // next item; reset to 0 by each launch
   const BatchInst* inst;
+  int64_t n_inst;
   const BatchItem* items;
   int64_t n_items;
   double theta_s, theta_d, var_init, var_floor, mask_floor;
@@ -96,8 +105,9 @@ enum : int { FWD_BG = 1, FWD_CODES = 2, FWD_CKPT = 4, FWD_PRINTED = 8 };
 
 // flags: FWD_BG and FWD_PRINTED only
 const void* batched_kernel_symbol(int in_dtype, int acc, int P, int flags);
+// counts: some instance has foreground counters (cleared before the launch)
 hipError_t launch_batched(const BatchArgs& a, int in_dtype, int acc, int P, int flags, int grid,
-                          hipStream_t stream);
+                          bool counts, hipStream_t stream);
 
 // in_dtype: 0 f64, 1 f32, 2 bf16; acc: 0 f64, 1 f32, 2 f64 state with f32 bg and
 // gradients, 4 f32x2 state with f32 bg and gradients; P in {1, 2, 4}; flags FWD_*

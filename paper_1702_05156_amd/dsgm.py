@@ -96,7 +96,8 @@ class _GradState(ctypes.Structure):
 class Instance(ctypes.Structure):
     """dsgm_instance"""
     _fields_ = [("shape", Shape), ("frames", ctypes.c_void_p), ("state", _State),
-                ("masks", ctypes.c_void_p), ("bg", ctypes.c_void_p)]
+                ("masks", ctypes.c_void_p), ("bg", ctypes.c_void_p),
+                ("fg_counts", ctypes.c_void_p)]
 
 
 class BatchPlan(ctypes.Structure):
@@ -104,7 +105,8 @@ class BatchPlan(ctypes.Structure):
     _fields_ = [("device_plan", ctypes.c_void_p), ("n_items", ctypes.c_int64),
                 ("total_elements", ctypes.c_int64), ("n_instances", ctypes.c_int32),
                 ("in_dtype", ctypes.c_int32), ("acc", ctypes.c_int32), ("vector", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("has_bg", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("has_bg", ctypes.c_int32),
+                ("has_counts", ctypes.c_int32)]
 
 
 def _load():
@@ -643,20 +645,27 @@ class DSGMFunction(torch.autograd.Function):
 
 
 # ------------------------------------------------------------------ batched
-def _instance(frames: torch.Tensor, state: State, masks: torch.Tensor, bg=None, acc=None) -> Instance:
+def _instance(frames: torch.Tensor, state: State, masks: torch.Tensor, bg=None, counts=None,
+              acc=None) -> Instance:
     sh = _frames_shape(frames)
     acc = _resolve_acc(state, acc)
     _same_layout("masks", masks, frames, torch.uint8)
     _same_layout("bg", bg, frames, ACC_TORCH[acc])
+    if counts is not None and (counts.dtype != torch.int32 or not counts.is_cuda or
+                               not counts.is_contiguous() or counts.numel() != sh.T):
+        raise ValueError(f"counts: need a contiguous int32 CUDA tensor of {sh.T} entries")
     return Instance(sh, frames.data_ptr(), _cstate(state, sh.H, sh.W), masks.data_ptr(),
-                    None if bg is None else bg.data_ptr())
+                    None if bg is None else bg.data_ptr(),
+                    None if counts is None else counts.data_ptr())
 
 
 class Batch:
     """Many independent instances planned for one persistent launch.
 
-    ``items`` is a list of (frames, state, masks, bg-or-None); every tensor is
-    kept alive by this object.  ``run(params)`` calls dsgm_forward_batched on the
+    ``items`` is a list of (frames, state, masks, bg-or-None[, counts-or-None]);
+    counts is an int32 tensor of T entries that each run fills with the
+    foreground pixels of every frame.  Every tensor is kept alive by this
+    object.  ``run(params)`` calls dsgm_forward_batched on the
     current stream (capturable into a CUDA/HIP graph).
     """
 

@@ -210,8 +210,15 @@ def _inst(T=4, H=8, W=8, ptr=FAKE, bg=None):
 def test_batched_validation():
     one = (dsgm.Instance * 2)(_inst(), _inst(T=3, H=4, W=12))
     n = lib.dsgm_batch_plan_bytes(one, 2, 1, 1)
-    # header + 2 descriptors (padded) + items: 8*8/4 = 16 groups -> 1 item; 4*12/4 -> 1 item
-    assert n == 256 + 256 + 256
+    # header + 2 descriptors of 136 B (padded) + items: 8*8/4 = 16 groups -> 1 item;
+    # 4*12/4 -> 1 item
+    assert n == 256 + 512 + 256
+    # foreground counters add 256 stripes of T counters per instance (padded)
+    cnt = (dsgm.Instance * 2)(_inst(), _inst(T=3, H=4, W=12))
+    cnt[1].fg_counts = FAKE
+    assert lib.dsgm_batch_plan_bytes(cnt, 2, 1, 1) == n + 3 * 256 * 4
+    cnt[1].fg_counts = FAKE + 2
+    assert lib.dsgm_batch_plan_bytes(cnt, 2, 1, 1) == 0   # misaligned counters
     assert lib.dsgm_batch_plan_bytes(None, 2, 1, 1) == 0
     bad = (dsgm.Instance * 1)(_inst(ptr=FAKE + 2))
     assert lib.dsgm_batch_plan_bytes(bad, 1, 1, 1) == 0   # misaligned f32 frames

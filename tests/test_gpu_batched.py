@@ -111,7 +111,7 @@ def test_batched_lpt_order_and_plan():
     # item table: costs non-increasing
     hdr = 256
     ninst = len(SHAPES)
-    inst_bytes = ((ninst * 120 + 255) // 256) * 256  # sizeof(BatchInst) = 120
+    inst_bytes = ((ninst * 136 + 255) // 256) * 256  # sizeof(BatchInst) = 136
     raw = batch.plan_buffer.cpu().numpy()
     it = raw[hdr + inst_bytes: hdr + inst_bytes + 16 * batch.plan.n_items].view(np.int32).reshape(-1, 4)
     T = np.array([s[0] for s in SHAPES])
@@ -156,6 +156,64 @@ def test_batched_graph_capture_replays():
             for a, c in zip(st.planes(), ws):
                 assert torch.equal(a, c), rep
         # some eager work between replays
+        torch.ones(1000, device="cuda").sum().item()
+
+
+@pytest.mark.parametrize("in_dtype,acc_dtype", [(torch.bfloat16, torch.float32),
+                                                (torch.float64, torch.float64)])
+def test_batched_foreground_counts(in_dtype, acc_dtype):
+    """Per-frame foreground counts of the instances that ask for them, equal to
+    the count of 255s in their masks (exact integers), nothing written for the
+    others; every replay of a captured launch clears and recounts them."""
+    p = dsgm.dsgm_params_default(2.0)
+    items, _ = _make(SHAPES, in_dtype, acc_dtype, bg=False, seed0=700)
+    sentinel = -7
+    counts = [torch.full((T,), sentinel, dtype=torch.int32, device="cuda") if i % 3 != 1 else None
+              for i, (T, H, W) in enumerate(SHAPES)]
+    items = [it[:3] + (None, c) for it, c in zip(items, counts)]
+    init = [st.clone() for _, st, *_ in items]
+    batch = dsgm.Batch(items)
+    assert batch.plan.has_counts == 1
+
+    def check(tag):
+        for i, ((fr, st, masks, _, c), (T, H, W)) in enumerate(zip(items, SHAPES)):
+            if c is None:
+                continue
+            if T * H * W == 0:
+                # no work: the counters are left as they were
+                assert bool((c == sentinel).all()), (tag, i)
+                continue
+            want = (masks.view(T, -1) == 255).sum(dim=1).to(torch.int32)
+            assert torch.equal(c, want), (tag, i, c[:8].tolist(), want[:8].tolist())
+            assert int(want.sum()) > 0
+
+    batch.run(p)
+    torch.cuda.synchronize()
+    check("eager")
+
+    def restore():
+        for (_, st, m, _, _), s0 in zip(items, init):
+            for a, b in zip(st.planes(), s0.planes()):
+                a.copy_(b)
+            m.zero_()
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    restore()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=s):
+        batch.run(p)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        restore()
+        for c, (T, H, W) in zip(counts, SHAPES):
+            if c is not None and T * H * W:
+                c.fill_(123456)  # stale values that the launch must clear
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        check(f"replay {rep}")
         torch.ones(1000, device="cuda").sum().item()
 
 
