@@ -60,7 +60,11 @@ typedef enum {
 } dsgm_status;
 
 /* storage type of the frames (U8: 8-bit frames, 0..255, for the as-run model) */
-typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2, DSGM_IN_U8 = 3 } dsgm_in_dtype;
+/* The _RANGE_ members of this and the next enum are not valid arguments: they
+ * make every int32 value a value of the type, so that any integer a caller
+ * passes can be read and rejected (DSGM_E_DTYPE) without undefined behaviour. */
+typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2, DSGM_IN_U8 = 3,
+               DSGM_IN_RANGE_MIN_ = -2147483647 - 1, DSGM_IN_RANGE_MAX_ = 2147483647 } dsgm_in_dtype;
 
 /* type of the model state and of every arithmetic operation, and of the bulk
  * output arrays (bg and every gradient array):
@@ -86,7 +90,8 @@ typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2, DSGM_IN_U8 = 
  *             dsgm_forward, dsgm_backward(_noalloc), dsgm_state_init_from_frame
  *             and the tuner; other calls return DSGM_E_DTYPE */
 typedef enum { DSGM_ACC_F64 = 0, DSGM_ACC_F32 = 1, DSGM_ACC_F64_IO32 = 2, DSGM_ACC_U8 = 3,
-               DSGM_ACC_F32X2 = 4 } dsgm_acc;
+               DSGM_ACC_F32X2 = 4,
+               DSGM_ACC_RANGE_MIN_ = -2147483647 - 1, DSGM_ACC_RANGE_MAX_ = 2147483647 } dsgm_acc;
 
 /* learning weight of a model of age a: Sec. 2.2 gives 1/(a+1); the appendix
  * computes 1/a.  The complementary weight is 1 - w in the accumulation type. */
