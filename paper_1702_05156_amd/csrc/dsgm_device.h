@@ -249,6 +249,8 @@ __device__ __forceinline__ StepRecord<Acc> step_core(Model<Acc>& s, const Acc x,
   r.hitC = hitC && !hitA;
   r.swap = s.aC > s.aA;
   r.fg = false;
+  r.qA = qA;
+  r.V = V;
   return r;
   }
 }
@@ -275,22 +277,54 @@ __device__ __forceinline__ bool fg_of(const Model<Acc>& s, const Acc x, const St
   return !((qd <= k.theta_d * ref) | (qd <= k.td_mf));
 }
 
-// The mask of the step given its record.  With f32x2 the squared distance
-// (mA - x)^2 after the step is one the step already formed: mA is the updated
-// model if A matched (d*d), the promoted C after an exchange (d*d if C
-// matched, else its untouched distance qC), and otherwise unchanged (qA).
+// The squared distance (mA - x)^2 of the background test, taken from the
+// step where it already formed it: mA after the step is the updated model if
+// A matched (its d*d), else the untouched A (the A test's distance: x - mA is
+// the exact negation of mA - x, so the square is the same number).  An
+// exchange changes mA; mask_dist_swapped() then gives the promoted model's.
+template <typename Acc>
+__device__ __forceinline__ Acc mask_dist(const StepRecord<Acc>& r) {
+  if constexpr (is_f32x2<Acc>::value)
+    return x2::sel(r.hitA, r.V, r.qA);
+  else
+    return r.hitA ? r.V : r.qA;
+}
+
+// after an exchange (swap true): mA is the promoted C, updated (d*d) if C
+// matched; if A matched (possible only from a state whose C was older than A),
+// the untouched C (its test distance)
+template <typename Acc>
+__device__ __forceinline__ Acc mask_dist_swapped(const StepRecord<Acc>& r, const Model<Acc>& s,
+                                                 const Acc x, const Acc qd) {
+  if constexpr (is_f32x2<Acc>::value) {
+    return x2::sel(r.swap, x2::sel(r.hitA, r.qC, r.V), qd);
+  } else {
+    const Acc dd = s.mA - x;
+    return r.swap ? dd * dd : qd;
+  }
+}
+
+// The mask from the step's squared distance qd = (mA - x)^2 and the state
+// after the exchange.
 template <typename Acc, bool PRINTED>
-__device__ __forceinline__ bool fg_of(const Model<Acc>& s, const Acc x, const StepConsts<Acc>& k,
-                                      const StepRecord<Acc>& r) {
+__device__ __forceinline__ bool fg_from(const Acc qd, const Model<Acc>& s, const Acc x,
+                                        const StepConsts<Acc>& k) {
   if constexpr (is_f32x2<Acc>::value) {
     using namespace x2;
-    const f32x2 qd = sel(r.hitA != r.swap, r.V, sel(r.swap, r.qC, r.qA));
     const f32x2 ref = PRINTED ? x : s.vA;
     return !(le(qd, mul(k.theta_d, ref)) | le(qd, k.td_mf));
   } else {
-    (void)r;
-    return fg_of<Acc, PRINTED>(s, x, k);
+    const Acc ref = PRINTED ? x : s.vA;
+    return !((qd <= k.theta_d * ref) | (qd <= k.td_mf));
   }
+}
+
+// The mask of the step given its record (on the state after the exchange).
+template <typename Acc, bool PRINTED>
+__device__ __forceinline__ bool fg_of(const Model<Acc>& s, const Acc x, const StepConsts<Acc>& k,
+                                      const StepRecord<Acc>& r) {
+  const Acc qd = mask_dist_swapped<Acc>(r, s, x, mask_dist<Acc>(r));
+  return fg_from<Acc, PRINTED>(qd, s, x, k);
 }
 
 // One whole frame of one pixel (state updated in place).

@@ -180,22 +180,26 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
     Vec<Io, P> bgv;
     Vec<uint8_t, P> cd;
     // the P pixels' exchanges share one wavefront-uniform branch
-    Acc xs[P];
+    Acc xs[P], qd[P];
     StepRecord<Acc> r[P];
     bool any = false;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       xs[q] = to_acc<In, Acc>(xin.v[q]);
       r[q] = step_core<Acc>(s[q], xs[q], k, tbl);
+      qd[q] = mask_dist<Acc>(r[q]);
       any |= r[q].swap;
     }
     if (any_lane(any)) {
 #pragma unroll
-      for (int q = 0; q < P; ++q) apply_swap<Acc>(s[q], xs[q], k, r[q].swap);
+      for (int q = 0; q < P; ++q) {
+        apply_swap<Acc>(s[q], xs[q], k, r[q].swap);
+        qd[q] = mask_dist_swapped<Acc>(r[q], s[q], xs[q], qd[q]);
+      }
     }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      r[q].fg = fg_of<Acc, PRINTED>(s[q], xs[q], k, r[q]);
+      r[q].fg = fg_from<Acc, PRINTED>(qd[q], s[q], xs[q], k);
       mk.v[q] = r[q].fg ? uint8_t(255) : uint8_t(0);
       if (BG) bgv.v[q] = Io(s[q].mA);  // rounded once when Io is narrower
       if (CODES) cd.v[q] = uint8_t(code_of<Acc>(r[q]));
