@@ -435,7 +435,7 @@ size_t dsgm_autotune_bytes(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shap
  * makes that measurement for the caller's problem: it times dsgm_forward on
  * min(T, 64) frames of H x W independent uniform intensities (dense layout,
  * default parameters for the frame type's range, the outputs that `flags`
- * names) for every workgroup size 64, 128, 256 and every pixels-per-lane width
+ * names) for every workgroup size 64, 128, 192, 256 and every pixels-per-lane width
  * 1, 2, 4 that W allows, each from the same initial state, and keeps the
  * fastest in a process-wide table under the key (in_dtype, acc, H, W, flags).
  * Later dsgm_forward calls whose arguments have that key launch with the

@@ -540,14 +540,16 @@ int dsgm_autotune(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape, int32_
   }
   // two rounds over the candidates, each candidate's time the better of its
   // two (interleaving keeps clock and cache drift from favouring one)
-  const int blocks[3] = {64, 128, 256}, vectors[3] = {1, 2, 4};
+  // (192 is the FP64 forward's default: the table must be able to hold it)
+  constexpr int kBlocks = 4, kVectors = 3, kCand = kBlocks * kVectors;
+  const int blocks[kBlocks] = {64, 128, 192, 256}, vectors[kVectors] = {1, 2, 4};
   constexpr int kReps = 4, kRounds = 2;
-  float best_ms[9];
-  for (int c = 0; c < 9; ++c) best_ms[c] = -1.f;
+  float best_ms[kCand];
+  for (int c = 0; c < kCand; ++c) best_ms[c] = -1.f;
   rc = DSGM_OK;
   for (int round = 0; round < kRounds && rc == DSGM_OK; ++round) {
-    for (int c = 0; c < 9 && rc == DSGM_OK; ++c) {
-      const int b = blocks[c / 3], v = vectors[c % 3];
+    for (int c = 0; c < kCand && rc == DSGM_OK; ++c) {
+      const int b = blocks[c / kVectors], v = vectors[c % kVectors];
       if (shape.W % v) continue;
       // every candidate starts from the same state; one untimed call warms up
       if ((rc = dsgm_state_init_from_frame(frames, in_dtype, L.shape, acc, &p, &st, stream)))
@@ -572,10 +574,10 @@ int dsgm_autotune(dsgm_in_dtype in_dtype, dsgm_acc acc, dsgm_shape shape, int32_
     }
   }
   int best = -1;
-  for (int c = 0; c < 9; ++c)
+  for (int c = 0; c < kCand; ++c)
     if (best_ms[c] >= 0.f && (best < 0 || best_ms[c] < best_ms[best])) best = c;
-  const int best_block = best >= 0 ? blocks[best / 3] : 256;
-  const int best_vector = best >= 0 ? vectors[best % 3] : 1;
+  const int best_block = best >= 0 ? blocks[best / kVectors] : 256;
+  const int best_vector = best >= 0 ? vectors[best % kVectors] : 1;
   (void)hipEventDestroy(e0);  // release failures change nothing for the caller
   (void)hipEventDestroy(e1);
   if (rc != DSGM_OK) return rc;

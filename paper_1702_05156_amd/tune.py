@@ -30,7 +30,7 @@ import torch
 
 from . import dsgm
 
-BLOCKS = (64, 128, 256)
+BLOCKS = (64, 128, 192, 256)
 VECTORS = (1, 2, 4)
 _lock = threading.Lock()
 

@@ -85,7 +85,7 @@ def test_native_autotune_chooses_and_applies(in_dtype, acc_dtype, acc, flags, W)
     dsgm.dsgm_autotune_clear()
     in_code = dsgm._IN_DTYPES[in_dtype]
     chosen = dsgm.dsgm_autotune(in_code, acc, T, H, W, flags)
-    assert chosen[0] in (64, 128, 256) and chosen[1] in (1, 2, 4) and W % chosen[1] == 0
+    assert chosen[0] in (64, 128, 192, 256) and chosen[1] in (1, 2, 4) and W % chosen[1] == 0
     assert dsgm.dsgm_autotune_lookup(in_code, acc, T, H, W, flags) == chosen
     assert dsgm.dsgm_autotune_lookup(in_code, acc, T, H, W + 4, flags) == (0, 0)
     p = dsgm.dsgm_params_default(2.0)
@@ -129,7 +129,7 @@ def test_native_autotune_u8_and_empty():
     dsgm.dsgm_autotune_clear()
     assert dsgm.dsgm_autotune(dsgm.IN_U8, dsgm.ACC_U8, 0, H, W) == (0, 0)
     chosen = dsgm.dsgm_autotune(dsgm.IN_U8, dsgm.ACC_U8, T, H, W, dsgm.TUNE_PRINTED)
-    assert chosen[0] in (64, 128, 256) and chosen[1] in (1, 2, 4)
+    assert chosen[0] in (64, 128, 192, 256) and chosen[1] in (1, 2, 4)
     p = dsgm.dsgm_params_default(255.0, dsgm.MASK_PRINTED)
     p.weight_rule = dsgm.WEIGHT_APPENDIX
     fr = (sdev.frames(45, T, H, W, torch.float32) * 127.5 + 127.5).to(torch.uint8)
@@ -141,3 +141,35 @@ def test_native_autotune_u8_and_empty():
     assert torch.equal(tuned["masks"], ref["masks"])
     for a, b in zip(tuned_st.planes(), ref_st.planes()):
         assert torch.equal(a, b)
+
+
+def test_native_autotune_is_not_slower_than_the_default():
+    """On the FP64 forward (whose default, 192 threads at two pixels per lane,
+    is one of the candidates) the tuned shape runs no slower than the default
+    within noise: medians of interleaved timings, 10 % slack."""
+    import statistics
+    T, H, W = 64, 480, 640
+    dsgm.dsgm_autotune_clear()
+    chosen = dsgm.dsgm_autotune(dsgm.IN_F64, dsgm.ACC_F64, T, H, W)
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st = G.device_case(46, T, H, W)
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+
+    def once():
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dsgm.dsgm_forward(fr, st, p, masks)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    tuned, default = [], []
+    for _ in range(2):
+        once()  # warm up both
+    for _ in range(7):
+        tuned.append(once())               # the table holds the tuned shape
+        dsgm.dsgm_set_launch(192, 2)       # the FP64 default, forced
+        default.append(once())
+        dsgm.dsgm_set_launch(0, 0)
+    dsgm.dsgm_autotune_clear()
+    assert statistics.median(tuned) <= 1.10 * statistics.median(default), (chosen, tuned, default)
