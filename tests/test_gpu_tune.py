@@ -21,7 +21,7 @@ def test_tune_forward_caches_and_applies(tmp_path, monkeypatch):
     fr, st = G.device_case(41, T, H, W, torch.float32, torch.float32)
     before = st.clone()
     r = tune.tune_forward(fr, st, p, reps=2)
-    assert len(r["candidates"]) == 9
+    assert len(r["candidates"]) == len(tune.BLOCKS) * 3 == 12
     for a, b in zip(st.planes(), before.planes()):
         assert torch.equal(a, b)  # the caller's state is untouched
     key = tune.forward_key(fr, st)
