@@ -223,3 +223,47 @@ def test_full_size_f32x2_forward_and_adjoint_sampled():
         _assert_rounded_once(f"grad_state0[{i}]", r["grad_state0"][i].view(-1)[pt].cpu().numpy(),
                              rb["grad_state0"][i], tol=1e-11)
     del fr, st, masks, bg, ck, gbg, gst, r
+
+
+def test_f32x2_adjoint_matches_central_difference_of_the_pair_forward():
+    """The compensated adjoint against central differences of the compensated
+    forward, independently of the oracle: d/dh <gst, state_T(s0 + h u)> for a
+    direction u over the four initial float planes, h = 1e-6, against
+    <u, grad_state0>.  With the decisions fixed the final state is quadratic
+    in the initial one, so the quotient is exact up to rounding (the pairs
+    carry about 48 bits); pixels whose decisions change under the
+    perturbation are left out of the direction."""
+    T, H, W, seed, h = 60, 8, 32, 57, 1e-6
+    p = dsgm.dsgm_params_default(2.0)
+    fr, st, _, _ = _case(seed, T, H, W, torch.float32)
+    gst = tuple(g.contiguous() for g in sdev.grad_state(seed + 100, H, W, torch.float32))
+    s0 = [dsgm.x2_to_f64(t) for t in st.planes()[:4]]
+    dirs = [sdev.fill(torch.empty((H, W), dtype=torch.float64, device="cuda"), seed + i,
+                      synth.STREAM_DIRECTION) for i in range(4)]
+    keep = torch.ones((H, W), dtype=torch.float64, device="cuda")
+
+    def objective(step):
+        planes = [dsgm.x2_from_f64(s0[i] + step * dirs[i] * keep) for i in range(4)]
+        s = dsgm.State(*planes, st.age_a.clone(), st.age_c.clone())
+        o = dsgm.forward(fr, s, p, codes=True)
+        val = sum((g.double() * dsgm.x2_to_f64(pl)).sum(dtype=torch.float64)
+                  for g, pl in zip(gst, (s.mean_a, s.var_a, s.mean_c, s.var_c)))
+        return float(val.item()), o["codes"]
+
+    _, codes0 = objective(0.0)
+    for _ in range(3):
+        fp, cp = objective(h)
+        fm, cm = objective(-h)
+        changed = ((cp != codes0) | (cm != codes0)).any(dim=0)
+        if not bool(changed.any()):
+            break
+        keep = keep * (~changed).double()
+    assert not bool(changed.any())
+    fd = (fp - fm) / (2 * h)
+    s = st.clone()
+    o = dsgm.forward(fr, s, p, ckpt_every=16)
+    r = dsgm.backward(fr, p, o["ckpt"], 16, X2, None, gst)
+    an = sum(float((dirs[i] * keep * r["grad_state0"][i].double()).sum(dtype=torch.float64).item())
+             for i in range(4))
+    assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (fd, an)
+    assert float(keep.mean()) > 0.9
