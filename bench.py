@@ -64,9 +64,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # FP32: the published 157.3 TFLOP/s vector peak -> 78.6 T.  That figure is
 # quoted for packed FP32, which this build does not emit; it is still the
 # ceiling used, because 32-bit VALU instructions measurably retire faster than
-# 64 lanes per CU per clock here: the BF16/FP32 forward's counters give 40.3
+# 64 lanes per CU per clock here: the BF16/FP32 forward's counters give 39.3
 # VALU wavefront instructions x 64 lanes per element over 2.4576 G elements in
-# 2.0727 ms, i.e. 47.8 T lane-ops/s, above the 39.3 T that a 64-lane issue
+# 2.0108 ms, i.e. 48.0 T lane-ops/s, above the 39.3 T that a 64-lane issue
 # limit allows (profiles/counters_all_kernels.md, row `fwd_kernel<dsgm::bf16_t,
 # float, float, 4, 4, 0>`).  With the 39.3 T figure that kernel would run at
 # 122 % of its ceiling.
