@@ -808,7 +808,7 @@ def leg_batched(args, dsgm, sdev, torch):
     # the tile width (pixels per lane) of the plan is picked by the autotuner
     from paper_1702_05156_amd import tune
     tuned = tune.tune_batched(items, p, store=False)
-    batch = dsgm.Batch(items, vector=tuned["vector"])
+    batch = dsgm.Batch(items, vector=tuned["vector"], grid=tuned["grid"])
     batch.run(p)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -873,7 +873,9 @@ def leg_batched(args, dsgm, sdev, torch):
            "instances": len(shapes), "total_elements": int(elems), "work_items": n_items,
            "persistent_workgroups": grid,
            "autotuned_pixels_per_lane": tuned["vector"],
-           "autotune_candidates_ms": {str(c["vector"]): round(c["ms"], 3) for c in tuned["candidates"]},
+           "autotuned_grid_fraction": tuned["grid_fraction"],
+           "autotune_candidates_ms": {f'{c["vector"]}px/{c["grid"]}wg': round(c["ms"], 3)
+                                      for c in tuned["candidates"]},
            "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
            "roofline": roof(alg, float(sum(kk) / len(kk)), elems, OPS_STEP, True),
            "fp64_form": {"workload": "the same 512 instances, fp64 frames (same values) and fp64 "

@@ -356,7 +356,9 @@ typedef struct {
   int32_t n_instances;
   int32_t in_dtype, acc;
   int32_t vector;         /* pixels per lane, common to all instances         */
-  int32_t grid;           /* persistent workgroups (device-resident count)    */
+  int32_t grid;           /* persistent workgroups: the planner sets the count
+                             that fills the device; the caller may lower it to
+                             any value >= 1 (results do not depend on it)     */
   int32_t has_bg;
   int32_t has_counts;     /* some instance has foreground counters            */
 } dsgm_batch_plan;

@@ -1144,6 +1144,7 @@ int dsgm_forward_batched(const dsgm_batch_plan* plan, const dsgm_params* params,
   if ((rc = check_params(params))) return rc;
   if (plan->vector != 1 && plan->vector != 2 && plan->vector != 4)
     return fail(DSGM_E_ARG, "plan.vector = %d invalid", plan->vector);
+  if (plan->grid < 1) return fail(DSGM_E_ARG, "plan.grid = %d: at least one workgroup", plan->grid);
   if (plan->n_items == 0) return ok();
   char* base = static_cast<char*>(plan->device_plan);
   dsgm::BatchArgs a;

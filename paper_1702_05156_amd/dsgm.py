@@ -669,9 +669,11 @@ class Batch:
     current stream (capturable into a CUDA/HIP graph).
     """
 
-    def __init__(self, items, in_dtype=None, acc=None, vector: int = 0):
+    def __init__(self, items, in_dtype=None, acc=None, vector: int = 0, grid: int = 0):
         """``vector`` (pixels per lane, 1/2/4; 0 = the library's default) is the
-        tile width of the plan; ``tune.tune_batched`` picks it by measurement."""
+        tile width of the plan and ``grid`` (0 = the planner's device-filling
+        count) the number of persistent workgroups; ``tune.tune_batched`` picks
+        both by measurement."""
         self.items = list(items)
         if not self.items:
             raise ValueError("empty batch")
@@ -698,6 +700,10 @@ class Batch:
         finally:
             if vector:
                 dsgm_set_launch(0, 0)
+        if grid:
+            if grid < 1:
+                raise ValueError(f"grid = {grid}: at least one workgroup")
+            self.plan.grid = int(grid)
 
     def run(self, params: Params) -> None:
         _check("dsgm_forward_batched",

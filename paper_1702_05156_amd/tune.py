@@ -14,10 +14,12 @@ file keyed by the problem's types, output set and sizes:
 ``tuned(key)`` is a context manager that applies a cached shape through
 ``dsgm_set_launch`` for the calls inside it (the setting is per process).
 
-``tune_batched`` does the same for a batch of uneven instances: it plans the
-batch with each tile width (pixels per lane: 1, 2, 4), times one persistent
-launch of each, and returns (and caches) the fastest; ``Batch(items,
-vector=best["vector"])`` then plans with it.
+``tune_batched`` does the same for a batch of uneven instances over two
+dimensions: the tile width (pixels per lane: 1, 2, 4), with which it plans the
+batch, and the number of persistent workgroups (the planner's device-filling
+count, three quarters and half of it).  It times one launch of each pair and
+returns (and caches) the fastest; ``Batch(items, vector=best["vector"],
+grid=best["grid"])`` then plans with it.
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ from . import dsgm
 
 BLOCKS = (64, 128, 192, 256)
 VECTORS = (1, 2, 4)
+GRID_FRACTIONS = (1.0, 0.75, 0.5)  # of the planner's device-filling persistent grid
 _lock = threading.Lock()
 
 
@@ -143,10 +146,12 @@ def batched_key(items) -> str:
 
 
 def tune_batched(items, params: "dsgm.Params", *, reps: int = 2, store: bool = True) -> dict:
-    """Time one persistent batched launch per tile width on these instances.
+    """Time one persistent batched launch per (tile width, persistent grid) pair
+    on these instances.
 
     The instances' states advance with every launch (the timing does not
-    depend on the values).  Returns and caches {"vector", "ms", "candidates"}.
+    depend on the values).  Returns and caches {"vector", "grid",
+    "grid_fraction", "ms", "candidates"}.
     """
     results = []
     stream = torch.cuda.current_stream()
@@ -158,16 +163,21 @@ def tune_batched(items, params: "dsgm.Params", *, reps: int = 2, store: bool = T
                 continue
             if b.plan.vector != vec:
                 continue  # a layout the instances do not allow
-            b.run(params)  # warm
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                b.run(params)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            results.append({"vector": vec, "ms": e0.elapsed_time(e1) / reps,
-                            "work_items": int(b.plan.n_items)})
+            full = int(b.plan.grid)
+            for frac in GRID_FRACTIONS:
+                grid = max(1, int(round(full * frac)))
+                b.plan.grid = grid
+                b.run(params)  # warm
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    b.run(params)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                results.append({"vector": vec, "grid": grid, "grid_fraction": frac,
+                                "ms": e0.elapsed_time(e1) / reps,
+                                "work_items": int(b.plan.n_items)})
             del b
     if not results:
         raise RuntimeError("no tile width is allowed by these instances")
@@ -177,6 +187,7 @@ def tune_batched(items, params: "dsgm.Params", *, reps: int = 2, store: bool = T
         key = batched_key(items)
         with _lock:
             cache = _load()
-            cache[key] = {"vector": best["vector"], "ms": best["ms"]}
+            cache[key] = {"vector": best["vector"], "grid": best["grid"],
+                          "grid_fraction": best["grid_fraction"], "ms": best["ms"]}
             _store(cache)
     return out

@@ -234,7 +234,9 @@ def test_batched_validation():
     plan.device_plan = FAKE
     plan.vector = 3
     assert lib.dsgm_forward_batched(ctypes.byref(plan), ctypes.byref(p), None) == -1
-    plan.vector, plan.n_items = 4, 0
+    plan.vector, plan.n_items, plan.grid = 4, 0, 0
+    assert lib.dsgm_forward_batched(ctypes.byref(plan), ctypes.byref(p), None) == -1  # no workgroups
+    plan.grid = 1
     assert lib.dsgm_forward_batched(ctypes.byref(plan), ctypes.byref(p), None) == 0  # nothing to do
 
 

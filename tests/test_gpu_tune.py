@@ -35,9 +35,10 @@ def test_tune_forward_caches_and_applies(tmp_path, monkeypatch):
 
 
 def test_tune_batched_picks_a_width_and_results_do_not_depend_on_it(tmp_path, monkeypatch):
-    """The batched autotuner times every tile width the instances allow; the
-    plan made with the chosen width gives the same masks and state as the
-    default plan."""
+    """The batched autotuner times every tile width the instances allow at
+    three persistent-grid sizes; the plan made with the chosen pair, and one
+    with a single workgroup, give the same masks and state as the default
+    plan."""
     monkeypatch.setenv("DSGM_TUNE_CACHE", str(tmp_path / "tune.json"))
     from paper_1702_05156_amd import tune
     p = dsgm.dsgm_params_default(2.0)
@@ -51,16 +52,19 @@ def test_tune_batched_picks_a_width_and_results_do_not_depend_on_it(tmp_path, mo
             items.append((fr, st, torch.empty((T, H, W), dtype=torch.uint8, device="cuda"), None))
         return items
     best = tune.tune_batched(make(), p)
-    assert best["vector"] in (1, 2, 4) and len(best["candidates"]) >= 2
-    assert tune.lookup(tune.batched_key(make()))["vector"] == best["vector"]
-    a, b = make(), make()
+    assert best["vector"] in (1, 2, 4) and len(best["candidates"]) >= 2 * len(tune.GRID_FRACTIONS)
+    assert {c["grid_fraction"] for c in best["candidates"]} == set(tune.GRID_FRACTIONS)
+    cached = tune.lookup(tune.batched_key(make()))
+    assert (cached["vector"], cached["grid"]) == (best["vector"], best["grid"]) and best["grid"] >= 1
+    a, b, c = make(), make(), make()
     dsgm.Batch(a).run(p)
-    dsgm.Batch(b, vector=best["vector"]).run(p)
+    dsgm.Batch(b, vector=best["vector"], grid=best["grid"]).run(p)
+    dsgm.Batch(c, grid=1).run(p)  # one persistent workgroup drains every item too
     torch.cuda.synchronize()
-    for (_, sa, ma, _), (_, sb, mb, _) in zip(a, b):
-        assert torch.equal(ma, mb)
-        for u, v in zip(sa.planes(), sb.planes()):
-            assert torch.equal(u, v)
+    for (_, sa, ma, _), (_, sb, mb, _), (_, sc, mc, _) in zip(a, b, c):
+        assert torch.equal(ma, mb) and torch.equal(ma, mc)
+        for u, v, w in zip(sa.planes(), sb.planes(), sc.planes()):
+            assert torch.equal(u, v) and torch.equal(u, w)
 
 
 def _same_forward(fr, st, p, **kw):
