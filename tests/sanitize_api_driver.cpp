@@ -217,6 +217,9 @@ static void batch_paths() {
   EXPECT(dsgm_forward_batched(&plan, &p, nullptr), DSGM_E_ARG);
   plan.vector = 2;
   plan.n_items = 0;
+  plan.grid = 0;
+  EXPECT(dsgm_forward_batched(&plan, &p, nullptr), DSGM_E_ARG);
+  plan.grid = 1;
   EXPECT(dsgm_forward_batched(&plan, &p, nullptr), DSGM_OK);
 }
 
