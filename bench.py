@@ -90,7 +90,7 @@ OPS_U8 = 22 + 12    # + the 8-bit storage rule on 4 values
 # that unit includes (a change anywhere else does not change the kernel)
 KERNEL_SOURCES = {
     "fwd_kernel_f64_f64_p2": ["dsgm_fwd_f64_f64.hip", "dsgm_fwd_impl.h", "dsgm_internal.h",
-                              "dsgm_device.h", "dsgm_f32x2.h"],
+                              "dsgm_device.h", "dsgm_f32x2.h", "dsgm_geom.h"],
 }
 
 

@@ -16,6 +16,7 @@
 #include "dsgm.h"
 #include "dsgm_ext.h"
 #include "dsgm_internal.h"
+#include "dsgm_plan.h"
 
 namespace {
 
@@ -48,7 +49,7 @@ size_t io_size(int a) { return a == DSGM_ACC_F64 ? 8 : 4; }
 
 bool aligned(const void* p, size_t n) { return (reinterpret_cast<uintptr_t>(p) % n) == 0; }
 
-int64_t pad256(int64_t b) { return (b + 255) / 256 * 256; }
+int64_t pad256(int64_t b) { return dsgm::geom::pad256(b); }
 
 int check_params(const dsgm_params* p) {
   if (!p) return fail(DSGM_E_ARG, "params is NULL");
@@ -185,7 +186,7 @@ int pick_vector(const dsgm_shape& s, const void* const* ptrs, const size_t* elem
 // ---------------------------------------------------------------- batching
 constexpr int64_t kPlanHeader = 256;  // the item counter lives here
 
-int64_t pad_to(int64_t b, int64_t a) { return (b + a - 1) / a * a; }
+int64_t pad_to(int64_t b, int64_t a) { return dsgm::geom::pad_to(b, a); }
 
 struct PlanLayout {
   int P = 4;
@@ -230,7 +231,7 @@ int plan_layout(const dsgm_instance* inst, int32_t n, int in_dtype, int acc, Pla
   for (int32_t i = 0; i < n; ++i) {
     const dsgm_shape& s = inst[i].shape;
     if (s.H * s.W == 0 || s.T == 0) continue;
-    items += (s.H * (s.W / P) + 63) / 64;
+    items += (s.H * (s.W / P) + dsgm::geom::ITEM_GROUPS - 1) / dsgm::geom::ITEM_GROUPS;
     total += s.T * s.H * s.W;
     if (inst[i].fg_counts) stripes += pad_to(s.T * dsgm::COUNT_STRIPES * 4, 256);
   }
@@ -290,10 +291,9 @@ size_t dsgm_ckpt_bytes(dsgm_shape shape, dsgm_acc acc, int32_t ckpt_every) {
       acc != DSGM_ACC_F32X2)
     return 0;
   if (ckpt_every < 1 || shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;
-  const int64_t n = (shape.T + ckpt_every - 1) / ckpt_every;
+  const int64_t n = dsgm::geom::ckpt_slots(shape.T, ckpt_every);
   const int64_t px = shape.H * shape.W;
-  const int64_t slot = 4 * pad256(px * int64_t(acc_size(acc))) + 2 * pad256(px);
-  return size_t(n * slot);
+  return size_t(n * dsgm::geom::ckpt_layout(px, int64_t(acc_size(acc))).slot);
 }
 
 int dsgm_state_init_from_frame(const void* frame0, dsgm_in_dtype in_dtype, dsgm_shape shape,
@@ -412,9 +412,10 @@ int forward_impl(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, d
   a.age_c = state->age_c;
   a.ckpt = ckpt;
   a.ckpt_every = ckpt ? ckpt_every : 1;
-  a.ckpt_fplane = pad256(px * int64_t(ae));
-  a.ckpt_aplane = pad256(px);
-  a.ckpt_slot_bytes = 4 * a.ckpt_fplane + 2 * a.ckpt_aplane;
+  const dsgm::geom::CkptLayout cl = dsgm::geom::ckpt_layout(px, int64_t(ae));
+  a.ckpt_fplane = cl.fplane;
+  a.ckpt_aplane = cl.aplane;
+  a.ckpt_slot_bytes = cl.slot;
   a.T = shape.T;
   a.H = shape.H;
   a.W = shape.W;
@@ -703,8 +704,8 @@ int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape
   a.W = shape.W;
   a.row_stride = shape.row_stride;
   a.frame_stride = shape.frame_stride;
-  a.tiles_x = (shape.W + 63) / 64;
-  a.tiles_y = (shape.H + 15) / 16;
+  a.tiles_x = (shape.W + dsgm::geom::pre::TW - 1) / dsgm::geom::pre::TW;
+  a.tiles_y = (shape.H + dsgm::geom::pre::TH - 1) / dsgm::geom::pre::TH;
   if (a.tiles_x * a.tiles_y >= (int64_t(1) << 31))
     return fail(DSGM_E_SHAPE, "too many tiles");
   a.theta_s = params->theta_s;
@@ -859,7 +860,7 @@ size_t dsgm_workspace_bytes(dsgm_shape shape, dsgm_acc acc) {
       acc != DSGM_ACC_F32X2)
     return 0;
   if (shape.T < 0 || shape.H < 0 || shape.W < 0) return 0;
-  return size_t(pad256(shape.H * shape.W * 8)) + dsgm::reduce_workspace_bytes();
+  return size_t(dsgm::geom::ws_bytes(shape.H * shape.W));
 }
 
 namespace {
@@ -916,7 +917,7 @@ int backward_validate(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape sha
 
 // The launches of the adjoint (arguments already validated), with the
 // per-pixel d/d(var_init) terms at gvi_px (H*W doubles, device) and the
-// reduction's partial sums at partial (dsgm::reduce_workspace_bytes() bytes,
+// reduction's partial sums at partial (2 * geom::REDUCE_BLOCKS doubles,
 // device).  Every pixel's term is written by the adjoint kernel and every
 // partial by the reduction, so neither buffer needs clearing.
 int backward_launch(const char* fn, const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
@@ -946,9 +947,10 @@ int backward_launch(const char* fn, const void* frames, dsgm_in_dtype in_dtype, 
     a.gs0_var_c = grad_state0->var_c;
     a.gvi_px = gvi_px;
     a.ckpt_every = ckpt_every >= 1 ? ckpt_every : 1;
-    a.ckpt_fplane = pad256(px * int64_t(ae));
-    a.ckpt_aplane = pad256(px);
-    a.ckpt_slot_bytes = 4 * a.ckpt_fplane + 2 * a.ckpt_aplane;
+    const dsgm::geom::CkptLayout cl = dsgm::geom::ckpt_layout(px, int64_t(ae));
+    a.ckpt_fplane = cl.fplane;
+    a.ckpt_aplane = cl.aplane;
+    a.ckpt_slot_bytes = cl.slot;
     a.T = shape.T;
     a.H = shape.H;
     a.W = shape.W;
@@ -1021,7 +1023,8 @@ int dsgm_backward(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape, 
     return fail(DSGM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
   const int64_t px = shape.H * shape.W;
   double* gvi_px = static_cast<double*>(workspace);
-  double* partial = reinterpret_cast<double*>(static_cast<char*>(workspace) + pad256(px * 8));
+  double* partial =
+      reinterpret_cast<double*>(static_cast<char*>(workspace) + dsgm::geom::ws_partial_offset(px));
   return backward_launch("dsgm_backward launch", frames, in_dtype, shape, acc, params, ckpt,
                          ckpt_every, grad_bg, grad_state_T, grad_frames, grad_state0,
                          grad_var_init, gvi_px, partial, stream);
@@ -1056,20 +1059,19 @@ size_t dsgm_batch_plan_bytes(const dsgm_instance* instances, int32_t n, dsgm_in_
   return size_t(L.bytes);
 }
 
-int dsgm_plan_batched(const dsgm_instance* instances, int32_t n, dsgm_in_dtype in_dtype,
-                      dsgm_acc acc, void* plan_buffer, size_t plan_bytes, dsgm_batch_plan* plan,
-                      hipStream_t stream) {
+}  // extern "C"
+
+namespace dsgm {
+
+int plan_image(const dsgm_instance* instances, int32_t n, int in_dtype, int acc, void* plan_buffer,
+               PlanImage* img) {
   PlanLayout L;
   int rc = plan_layout(instances, n, in_dtype, acc, &L);
   if (rc) return rc;
-  if (!plan) return fail(DSGM_E_ARG, "plan is NULL");
-  if (!plan_buffer) return fail(DSGM_E_ARG, "plan_buffer is NULL");
-  if (!aligned(plan_buffer, 256)) return fail(DSGM_E_ALIGN, "plan_buffer is not 256-byte aligned");
-  if (plan_bytes < size_t(L.bytes))
-    return fail(DSGM_E_WORKSPACE, "plan buffer of %zu bytes, %lld needed", plan_bytes,
-                (long long)L.bytes);
+  if (!img) return fail(DSGM_E_ARG, "plan image is NULL");
   const int P = L.P;
-  std::vector<char> host(size_t(L.bytes), 0);
+  std::vector<char>& host = img->host;
+  host.assign(size_t(L.bytes), 0);
   auto* desc = reinterpret_cast<dsgm::BatchInst*>(host.data() + L.inst_off);
   auto* items = reinterpret_cast<dsgm::BatchItem*>(host.data() + L.items_off);
   int64_t k = 0;
@@ -1101,10 +1103,10 @@ int dsgm_plan_batched(const dsgm_instance* instances, int32_t n, dsgm_in_dtype i
     d.groups_per_row = I.shape.W / P;
     if (I.shape.H * I.shape.W == 0 || I.shape.T == 0) continue;
     const int64_t ng = I.shape.H * (I.shape.W / P);
-    for (int64_t g = 0; g < ng; g += 64) {
+    for (int64_t g = 0; g < ng; g += dsgm::geom::ITEM_GROUPS) {
       items[k].inst = i;
       items[k].first_group = int32_t(g);
-      items[k].count = int32_t(std::min<int64_t>(64, ng - g));
+      items[k].count = int32_t(std::min<int64_t>(dsgm::geom::ITEM_GROUPS, ng - g));
       items[k].pad = 0;
       ++k;
     }
@@ -1113,26 +1115,56 @@ int dsgm_plan_batched(const dsgm_instance* instances, int32_t n, dsgm_in_dtype i
   std::stable_sort(items, items + k, [&](const dsgm::BatchItem& x, const dsgm::BatchItem& y) {
     return desc[x.inst].T * x.count > desc[y.inst].T * y.count;
   });
+  img->P = P;
+  img->n_items = L.n_items;
+  img->total = L.total;
+  img->inst_off = L.inst_off;
+  img->items_off = L.items_off;
+  img->stripes_off = L.stripes_off;
+  img->bytes = L.bytes;
+  img->bg = L.bg;
+  img->counts = L.counts;
+  return DSGM_OK;
+}
+
+}  // namespace dsgm
+
+extern "C" {
+
+int dsgm_plan_batched(const dsgm_instance* instances, int32_t n, dsgm_in_dtype in_dtype,
+                      dsgm_acc acc, void* plan_buffer, size_t plan_bytes, dsgm_batch_plan* plan,
+                      hipStream_t stream) {
+  PlanLayout L;
+  int rc = plan_layout(instances, n, in_dtype, acc, &L);
+  if (rc) return rc;
+  if (!plan) return fail(DSGM_E_ARG, "plan is NULL");
+  if (!plan_buffer) return fail(DSGM_E_ARG, "plan_buffer is NULL");
+  if (!aligned(plan_buffer, 256)) return fail(DSGM_E_ALIGN, "plan_buffer is not 256-byte aligned");
+  if (plan_bytes < size_t(L.bytes))
+    return fail(DSGM_E_WORKSPACE, "plan buffer of %zu bytes, %lld needed", plan_bytes,
+                (long long)L.bytes);
+  dsgm::PlanImage img;
+  if ((rc = dsgm::plan_image(instances, n, in_dtype, acc, plan_buffer, &img))) return rc;
   // persistent grid: as many 256-thread blocks as fit on the device at once
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const void* fn = dsgm::batched_kernel_symbol(in_dtype, acc, P, L.bg ? dsgm::FWD_BG : 0);
+  const void* fn = dsgm::batched_kernel_symbol(in_dtype, acc, img.P, img.bg ? dsgm::FWD_BG : 0);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
   if (e != hipSuccess) return hip_fail(e, "dsgm_plan_batched: device query");
-  e = hipMemcpyAsync(plan_buffer, host.data(), size_t(L.bytes), hipMemcpyHostToDevice, stream);
+  e = hipMemcpyAsync(plan_buffer, img.host.data(), size_t(img.bytes), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "dsgm_plan_batched: copy");
   plan->device_plan = plan_buffer;
-  plan->n_items = L.n_items;
-  plan->total_elements = L.total;
+  plan->n_items = img.n_items;
+  plan->total_elements = img.total;
   plan->n_instances = n;
   plan->in_dtype = in_dtype;
   plan->acc = acc;
-  plan->vector = P;
+  plan->vector = img.P;
   plan->grid = std::max(1, per_cu) * std::max(1, ncu);
-  plan->has_bg = L.bg ? 1 : 0;
-  plan->has_counts = L.counts ? 1 : 0;
+  plan->has_bg = img.bg ? 1 : 0;
+  plan->has_counts = img.counts ? 1 : 0;
   return ok();
 }
 

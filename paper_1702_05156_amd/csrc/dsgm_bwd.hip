@@ -73,7 +73,7 @@ bwd_kernel(const BwdArgs a) {
   }
 
   const int64_t T = a.T, K = a.ckpt_every;
-  const int64_t nseg = (T + K - 1) / K;
+  const int64_t nseg = geom::n_segments(T, K);
 
   // One chunk of `len` <= KC frames starting at c0, from state s: all of its
   // frame loads are issued before the taped replay, all of its upstream bg
@@ -134,13 +134,13 @@ bwd_kernel(const BwdArgs a) {
   };
 
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-    const int64_t s0 = seg * K;
-    const int64_t s1 = s0 + K < T ? s0 + K : T;
+    const geom::Range sg = geom::segment(seg, T, K);
+    const int64_t s0 = sg.lo;
     const char* base = ck + seg * a.ckpt_slot_bytes;
-    const int64_t nchunk = (s1 - s0 + KC - 1) / KC;
+    const int64_t nchunk = geom::n_chunks(sg, KC);
     for (int64_t c = nchunk - 1; c >= 0; --c) {
-      const int64_t c0 = s0 + c * KC;
-      const int64_t c1 = c0 + KC < s1 ? c0 + KC : s1;
+      const geom::Range ch = geom::chunk(sg, c, KC);
+      const int64_t c0 = ch.lo, c1 = ch.hi;
       Model<Acc> s;
       s.mA = reinterpret_cast<const Acc*>(base + 0 * a.ckpt_fplane)[g];
       s.vA = reinterpret_cast<const Acc*>(base + 1 * a.ckpt_fplane)[g];
@@ -197,7 +197,7 @@ __device__ __forceinline__ Pair pair_add(Pair x, Pair y) {
 }
 
 constexpr int RED_THREADS = 256;
-constexpr int RED_BLOCKS = 256;
+constexpr int RED_BLOCKS = geom::REDUCE_BLOCKS;
 static_assert(RED_BLOCKS == RED_THREADS, "pass 2 gives one pair to each thread");
 
 // pass 1: block b sums the contiguous chunk b of the input; thread i takes
@@ -256,8 +256,6 @@ hipError_t launch_bwd_k(const BwdArgs& a, hipStream_t stream) {
 }
 
 }  // namespace
-
-size_t reduce_workspace_bytes() { return size_t(2 * RED_BLOCKS) * sizeof(double); }
 
 hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* out,
                          hipStream_t stream) {

@@ -162,8 +162,11 @@ __device__ __forceinline__ StepRecord<f32x2> step_core_x2(Model<f32x2>& s, const
   const f32x2 qA = sqr(dA);
   const f32x2 dC = sub(x, s.mC);
   const f32x2 qC = sqr(dC);
-  const bool hitA = lt(qA, mul(k.theta_s, s.vA)) | lt(qA, k.ts_vf);
-  const bool hitC = lt(qC, mul(k.theta_s, s.vC)) | lt(qC, k.ts_vf);
+  // both comparisons of each test are evaluated (no short circuit)
+  const bool hA0 = lt(qA, mul(k.theta_s, s.vA)), hA1 = lt(qA, k.ts_vf);
+  const bool hC0 = lt(qC, mul(k.theta_s, s.vC)), hC1 = lt(qC, k.ts_vf);
+  const bool hitA = hA0 | hA1;
+  const bool hitC = hC0 | hC1;
   const bool reset = !hitA && !hitC;
 
   const int idx = hitA ? s.aA : (hitC ? s.aC : RESET_SLOT);
@@ -312,7 +315,8 @@ __device__ __forceinline__ bool fg_from(const Acc qd, const Model<Acc>& s, const
   if constexpr (is_f32x2<Acc>::value) {
     using namespace x2;
     const f32x2 ref = PRINTED ? x : s.vA;
-    return !(le(qd, mul(k.theta_d, ref)) | le(qd, k.td_mf));
+    const bool b0 = le(qd, mul(k.theta_d, ref)), b1 = le(qd, k.td_mf);
+    return !(b0 | b1);
   } else {
     const Acc ref = PRINTED ? x : s.vA;
     return !((qd <= k.theta_d * ref) | (qd <= k.td_mf));

@@ -98,13 +98,7 @@ struct CountArgs {
 hipError_t launch_count_nonfinite(const void* frames, int in_dtype, const CountArgs& a,
                                   hipStream_t stream);
 
-// Logical tile of workgroup b of nb: the hardware deals workgroups to the 8
-// XCDs round-robin (b mod 8), each XCD with its own L2; this bijection gives
-// XCD k the k-th contiguous share of the tiles, so tiles that share input rows
-// (stencil halos, the source rows of a warp) meet in the same L2.
-__device__ __forceinline__ int64_t tile_of(int64_t b, int64_t nb) {
-  const int64_t k = b % 8, i = b / 8, q = nb / 8, rem = nb % 8;
-  return k < rem ? k * (q + 1) + i : rem * (q + 1) + (k - rem) * q + i;
-}
+// logical tile of workgroup b of nb, XCD-contiguous (dsgm_geom.h)
+using geom::tile_of;
 
 }  // namespace dsgm

@@ -257,8 +257,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const FwdArgs a) {
 
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= a.ngroups) return;
-  const int64_t h = g / a.groups_per_row;
-  const int64_t w0 = (g - h * a.groups_per_row) * P;
+  const geom::Group G = geom::group_of(g, a.groups_per_row, P, a.W, a.row_stride);
   const StepConsts<Acc> k = make_consts<Acc>(a.theta_s, a.theta_d, a.var_init, a.var_floor,
                                              a.mask_floor);
   GroupJob j;
@@ -280,8 +279,8 @@ __global__ void __launch_bounds__(256) fwd_kernel(const FwdArgs a) {
   j.ckpt_aplane = a.ckpt_aplane;
   j.T = a.T;
   j.frame_stride = a.frame_stride;
-  j.foff = uint32_t(h * a.row_stride + w0);  // < 2^31 elements (host check)
-  j.soff = h * a.W + w0;
+  j.foff = uint32_t(G.foff);  // < 2^31 elements (host check)
+  j.soff = G.soff;
   run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl);
 }
 
@@ -350,8 +349,7 @@ __global__ void __launch_bounds__(256)
     const BatchInst I = wave_uniform(a.inst[it.inst]);
     if (lane < it.count) {
       const int64_t g = int64_t(it.first_group) + lane;
-      const int64_t h = g / I.groups_per_row;
-      const int64_t w0 = (g - h * I.groups_per_row) * P;
+      const geom::Group G = geom::group_of(g, I.groups_per_row, P, I.W, I.row_stride);
       GroupJob j;
       j.frames = static_cast<const char*>(I.frames);
       j.masks = reinterpret_cast<char*>(I.masks);
@@ -359,13 +357,13 @@ __global__ void __launch_bounds__(256)
       j.codes = nullptr;
       for (int q = 0; q < 6; ++q) j.state[q] = static_cast<char*>(I.state[q]);
       j.ckpt = nullptr;
-      j.counts = I.fg_counts ? I.stripes + int64_t(item % COUNT_STRIPES) * I.T : nullptr;
+      j.counts = I.fg_counts ? I.stripes + geom::stripe_of(item) * I.T : nullptr;
       j.ckpt_every = 1;
       j.ckpt_slot_bytes = j.ckpt_fplane = j.ckpt_aplane = 0;
       j.T = I.T;
       j.frame_stride = I.frame_stride;
-      j.foff = uint32_t(h * I.row_stride + w0);
-      j.soff = h * I.W + w0;
+      j.foff = uint32_t(G.foff);
+      j.soff = G.soff;
       // one body for instances with and without foreground counters (a
       // uniform run-time test per frame), so the kernel's code stays one copy
       run_item<In, Acc, Io, P, U, FLAGS | F_COUNT>(j, I, k, tbl);

@@ -36,10 +36,9 @@ __global__ void __launch_bounds__(256) grid_kernel(const GridArgs a) {
 
   const int64_t blk = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (blk >= a.Hb * a.Wb) return;  // no barrier follows
-  const int64_t by = blk / a.Wb, bx = blk - by * a.Wb;
-  const int64_t y0 = by * B, x0 = bx * B;
-  const int rows = int(a.H - y0 < B ? a.H - y0 : B);
-  const int cols = int(a.W - x0 < B ? a.W - x0 : B);
+  const geom::GridBlock gb = geom::grid_block(blk, a.Wb, B, a.H, a.W);
+  const int64_t y0 = gb.y0, x0 = gb.x0;
+  const int rows = gb.rows, cols = gb.cols;
   const bool whole = rows == B && cols == B;
   const bool vec = whole && a.vec_ok;
   const Acc n = Acc(rows * cols);

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "dsgm_device.h"
+#include "dsgm_geom.h"
 
 namespace dsgm {
 
@@ -57,8 +58,7 @@ struct BwdArgs {
 hipError_t launch_backward(const BwdArgs& a, int in_dtype, int acc, hipStream_t stream);
 
 // deterministic compensated sum of n doubles into out[0]; partial holds
-// reduce_workspace_bytes() bytes
-size_t reduce_workspace_bytes();
+// 2 * geom::REDUCE_BLOCKS doubles
 hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* out,
                          hipStream_t stream);
 
@@ -67,7 +67,7 @@ hipError_t launch_reduce(const double* x, int64_t n, double* partial, double* ou
 // copies (stripe = work item mod COUNT_STRIPES, each T counters) so that the
 // wavefronts working on one instance at the same time add to different
 // addresses; a last small kernel adds the stripes into the caller's counters.
-constexpr int COUNT_STRIPES = 256;
+constexpr int COUNT_STRIPES = int(geom::COUNT_STRIPES);
 
 struct BatchInst {
   const void* frames;

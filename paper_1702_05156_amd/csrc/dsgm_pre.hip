@@ -39,28 +39,13 @@ namespace pre {
 using fwd::fill_table;
 using fwd::make_consts;
 
-constexpr int TH = 16;   // tile rows
-constexpr int TW = 64;   // tile columns
-constexpr int PX = 4;    // pixels per lane (one row)
-constexpr int NT = 256;  // lanes per workgroup
-static_assert(TH * TW == NT * PX, "tile = lanes x pixels");
-
+// tile shape and every tile cell index: dsgm_geom.h
+using geom::pre::TH;
+using geom::pre::TW;
+using geom::pre::PX;
+using geom::pre::NT;
 template <int RG, bool MED>
-struct Geo {
-  static constexpr int RM = MED ? 1 : 0;       // median radius
-  static constexpr int R = RG + RM;            // halo of the raw tile
-  static constexpr int RAW_H = TH + 2 * R, RAW_W = TW + 2 * R;
-  static constexpr int HB_W = TW + 2 * RM;     // row-blurred: all raw rows, median halo columns
-  static constexpr int GB_H = TH + 2 * RM, GB_W = TW + 2 * RM;
-  static constexpr int RAW_N = RAW_H * RAW_W;
-  static constexpr int HB_N = RAW_H * HB_W;
-  static constexpr int GB_N = GB_H * GB_W;
-  static constexpr int LOADS = (RAW_N + NT - 1) / NT;  // raw elements per lane
-};
-
-__device__ __forceinline__ int64_t clampi(int64_t v, int64_t hi) {
-  return v < 0 ? 0 : (v > hi ? hi : v);
-}
+using Geo = geom::pre::Geo<RG, MED>;
 
 // min and max of finite values (v_min/v_max; a zero's sign may differ from a
 // sort's when +0 and -0 tie, which leaves every value unchanged)
@@ -86,7 +71,6 @@ __device__ __forceinline__ float tap<float>(float acc, float w, float x) {
 template <typename In, typename Acc, typename Io, int RG, bool MED, bool PRINTED>
 __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
   using G = Geo<RG, MED>;
-  constexpr int R = G::R, RM = G::RM;
   // raw, row-blurred and blurred tiles each have their own storage, so a frame
   // needs three barriers: the next frame's raw tile can be staged while slow
   // lanes still read this frame's blurred tile (without a blur the raw tile is
@@ -106,25 +90,23 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
   const int64_t tile = tile_of(blockIdx.x, gridDim.x);
   const int64_t y0 = (tile / a.tiles_x) * TH, x0 = (tile % a.tiles_x) * TW;
   const int tid = threadIdx.x;
-  const int ty = tid / (TW / PX), tx = (tid % (TW / PX)) * PX;  // this lane's row and first column
+  const int ty = G::lane_row(tid), tx = G::lane_col(tid);  // this lane's row and first column
   const int64_t gy = y0 + ty;
-  const int64_t H1 = a.H - 1, W1 = a.W - 1;
 
   // this lane's raw-tile elements: LDS slot and frame offset (both fixed per frame)
   uint32_t roff[G::LOADS];
 #pragma unroll
   for (int l = 0; l < G::LOADS; ++l) {
-    const int i = tid + l * NT;
-    const int r = i / G::RAW_W, c = i - r * G::RAW_W;
-    const int64_t yy = clampi(y0 - R + r, H1), xx = clampi(x0 - R + c, W1);
-    roff[l] = i < G::RAW_N ? uint32_t(yy * a.row_stride + xx) : 0u;  // < 2^31 (host check)
+    const int i = G::raw_cell(tid, l);
+    roff[l] = i < G::RAW_N ? uint32_t(G::raw_source(i, y0, x0, a.H, a.W, a.row_stride))
+                           : 0u;  // < 2^31 (host check)
   }
   // the median's rows and columns in the blurred tile, clamped to the frame
   int gr[3], gc[PX + 2];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) gr[d] = int(clampi(gy + d - 1, H1) - (y0 - RM));
+  for (int d = 0; d < 3; ++d) gr[d] = G::med_row(gy, d, y0, a.H);
 #pragma unroll
-  for (int d = 0; d < PX + 2; ++d) gc[d] = int(clampi(x0 + tx + d - 1, W1) - (x0 - RM));
+  for (int d = 0; d < PX + 2; ++d) gc[d] = G::med_col(x0 + tx, d, x0, a.W);
 
   bool valid[PX];
   bool all_valid = gy < a.H;
@@ -157,14 +139,10 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
   // this lane's outputs of the row and column passes (pairs of adjacent
   // outputs, lane-strided) and the row pass's window start in the raw tile:
   // the same every frame
-  constexpr int ROW_IT = (G::HB_N / 2 + NT - 1) / NT, COL_IT = (G::GB_N / 2 + NT - 1) / NT;
+  constexpr int ROW_IT = G::ROW_IT, COL_IT = G::COL_IT;
   uint32_t row_src[ROW_IT];
 #pragma unroll
-  for (int it = 0; it < ROW_IT; ++it) {
-    const int pi = tid + it * NT;
-    const int r = pi / (G::HB_W / 2), v = 2 * (pi - r * (G::HB_W / 2));
-    row_src[it] = uint32_t(r * G::RAW_W + v);
-  }
+  for (int it = 0; it < ROW_IT; ++it) row_src[it] = uint32_t(G::row_window(G::row_pair(tid, it)));
 
   const In* frames = static_cast<const In*>(a.frames);
   In nxt[G::LOADS];
@@ -172,7 +150,7 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
     const In* f = frames + t * a.frame_stride;
 #pragma unroll
     for (int l = 0; l < G::LOADS; ++l)
-      if (l + 1 < G::LOADS || tid + l * NT < G::RAW_N) nxt[l] = f[roff[l]];  // tid < NT
+      if (G::raw_active(tid, l)) nxt[l] = f[roff[l]];
   };
   if (a.T > 0) load_frame(0);
 
@@ -180,8 +158,7 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
     // 1. stage the raw tile, then start loading the next frame's
 #pragma unroll
     for (int l = 0; l < G::LOADS; ++l)
-      if (l + 1 < G::LOADS || tid + l * NT < G::RAW_N)
-        buf_raw[tid + l * NT] = to_acc<In, Acc>(nxt[l]);
+      if (G::raw_active(tid, l)) buf_raw[G::raw_cell(tid, l)] = to_acc<In, Acc>(nxt[l]);
     __syncthreads();
     if (t + 1 < a.T) load_frame(t + 1);
 
@@ -193,8 +170,8 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
       static_assert(G::HB_W % 2 == 0 && G::GB_W % 2 == 0, "output pairs stay in one row");
 #pragma unroll
       for (int it = 0; it < ROW_IT; ++it) {
-        const int pi = tid + it * NT;
-        if (it + 1 < ROW_IT || pi < G::HB_N / 2) {
+        const int pi = G::row_pair(tid, it);
+        if (G::row_active(tid, it)) {
           const Acc* src = buf_raw + row_src[it];
           Acc win[2 * RG + 2];
 #pragma unroll
@@ -215,8 +192,8 @@ __global__ void __launch_bounds__(NT) pre_kernel(const PreArgs a) {
       static_assert(G::HB_W == G::GB_W, "row-blurred and blurred tiles share a width");
 #pragma unroll
       for (int it = 0; it < COL_IT; ++it) {
-        const int pi = tid + it * NT;
-        if (it + 1 < COL_IT || pi < G::GB_N / 2) {
+        const int pi = G::col_pair(tid, it);
+        if (G::col_active(tid, it)) {
           const Acc* src = buf_hb + 2 * pi;
           Acc a0 = Acc(0), a1 = Acc(0);
 #pragma unroll

@@ -36,10 +36,8 @@ __global__ void __launch_bounds__(256) u8_kernel(const FwdArgs a) {
 
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= a.ngroups) return;  // no barrier follows
-  const int64_t h = g / a.groups_per_row;
-  const int64_t w = (g - h * a.groups_per_row) * P;
-  const int64_t pix = h * a.W + w;
-  const int64_t foff = h * a.row_stride + w;
+  const geom::Group G = geom::group_of(g, a.groups_per_row, P, a.W, a.row_stride);
+  const int64_t pix = G.soff, foff = G.foff;
 
   Model<double> s[P];
   {
@@ -147,10 +145,9 @@ __global__ void __launch_bounds__(256) u8_step_kernel(const FwdArgs a) {
   };
   // group g: row h, first column w (pixel index h*W + w, frame offset h*row_stride + w)
   auto offsets = [&](int64_t g, int64_t& pix, int64_t& foff) {
-    const int64_t h = g / a.groups_per_row;
-    const int64_t w = (g - h * a.groups_per_row) * P;
-    pix = h * a.W + w;
-    foff = h * a.row_stride + w;
+    const geom::Group G = geom::group_of(g, a.groups_per_row, P, a.W, a.row_stride);
+    pix = G.soff;
+    foff = G.foff;
   };
   auto load = [&](int64_t g, Bytes& b) {
     int64_t pix, foff;

@@ -63,18 +63,12 @@ __global__ void __launch_bounds__(256) warp_kernel(const WarpArgs a) {
   const int64_t fo = y * a.row_stride + c;  // frame / output offset
   const Acc x = to_acc<In, Acc>(static_cast<const In*>(a.frame)[fo]);
 
-  const double xd = double(c), yd = double(y);
-  const double den = (a.map[6] * xd + a.map[7] * yd) + a.map[8];
-  const double qx = ((a.map[0] * xd + a.map[1] * yd) + a.map[2]) / den;
-  const double qy = ((a.map[3] * xd + a.map[4] * yd) + a.map[5]) / den;
-  const bool covered = den > 0.0 && qx >= 0.0 && qx <= double(a.W - 1) && qy >= 0.0 &&
-                       qy <= double(a.H - 1);
+  // the source position and its neighbours (dsgm_geom.h)
+  const geom::WarpSrc src = geom::warp_source(c, y, a.map, a.H, a.W);
   Model<Acc> s;
-  if (covered) {
-    const double fx0 = floor(qx), fy0 = floor(qy);
-    const double fx = qx - fx0, fy = qy - fy0;
-    const int64_t x0 = int64_t(fx0), y0 = int64_t(fy0);
-    const int64_t x1 = x0 + 1 < a.W ? x0 + 1 : a.W - 1, y1 = y0 + 1 < a.H ? y0 + 1 : a.H - 1;
+  if (src.covered) {
+    const double fx = src.fx, fy = src.fy;
+    const int64_t x0 = src.x0, y0 = src.y0, x1 = src.x1, y1 = src.y1;
     const Acc w00 = Acc((1.0 - fx) * (1.0 - fy)), w10 = Acc(fx * (1.0 - fy));
     const Acc w01 = Acc((1.0 - fx) * fy), w11 = Acc(fx * fy);
     const Acc* mA = static_cast<const Acc*>(a.src_mean_a);
@@ -84,7 +78,7 @@ __global__ void __launch_bounds__(256) warp_kernel(const WarpArgs a) {
     if (a.W >= 2) {
       // each row's two neighbours come from one pair load at columns xa, xa+1
       // (xa = x0 except on the last column, where both neighbours are x0)
-      const int64_t xa = x0 < a.W - 1 ? x0 : a.W - 2;
+      const int64_t xa = src.xa;
       const bool lo = xa == x0;
       const int64_t r0 = y0 * a.W + xa, r1 = y1 * a.W + xa;
       auto gather = [&](const Acc* p) {
@@ -103,11 +97,8 @@ __global__ void __launch_bounds__(256) warp_kernel(const WarpArgs a) {
       s.mC = bilin(w00, mC[i00], w10, mC[i10], w01, mC[i01], w11, mC[i11]);
       s.vC = bilin(w00, vC[i00], w10, vC[i10], w01, vC[i01], w11, vC[i11]);
     }
-    int64_t xn = int64_t(floor(qx + 0.5)), yn = int64_t(floor(qy + 0.5));
-    xn = xn > a.W - 1 ? a.W - 1 : xn;
-    yn = yn > a.H - 1 ? a.H - 1 : yn;
-    s.aA = a.src_age_a[yn * a.W + xn];
-    s.aC = a.src_age_c[yn * a.W + xn];
+    s.aA = a.src_age_a[src.yn * a.W + src.xn];
+    s.aC = a.src_age_c[src.yn * a.W + src.xn];
   } else {
     s.mA = s.mC = x;
     s.vA = s.vC = k.var_init;
