@@ -95,6 +95,9 @@ def lib():
         _lib.orc_preprocess.argtypes = ([ctypes.c_int64] * 3 + [dp, dp, ctypes.c_int32, dp,
                                         ctypes.c_int32, ctypes.c_int])
         _lib.orc_preprocess.restype = ctypes.c_int
+        _lib.orc_preprocess_u8.argtypes = ([ctypes.c_int64] * 3 + [dp, dp, ctypes.c_int32, dp,
+                                           ctypes.c_int32, ctypes.c_int])
+        _lib.orc_preprocess_u8.restype = ctypes.c_int
         for f in (_lib.orc_forward, _lib.orc_backward, _lib.orc_jvp):
             f.restype = ctypes.c_int
     return _lib
@@ -237,6 +240,26 @@ def preprocess(frames, weights=None, median: bool = True, nthreads: int = 0) -> 
                               int(nthreads))
     if rc != 0:
         raise ValueError(f"orc_preprocess failed ({rc})")
+    return out
+
+
+def preprocess_u8(frames, weights=None, median: bool = True, nthreads: int = 0) -> np.ndarray:
+    """The appendix's 8-bit preprocessing (preprocess_oracle.c,
+    orc_preprocess_u8): a two-dimensional single-precision blur with the
+    window weights float(w_i * w_j), written back to 8 bits by dropping the
+    fraction, then the 3 x 3 median of the 8-bit image (None = no blur);
+    uint8 frames (T, H, W) -> same."""
+    x = np.ascontiguousarray(frames, dtype=np.uint8)
+    if x.ndim == 2:
+        x = x[None]
+    T, H, W = x.shape
+    out = np.empty_like(x)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    n = 0 if w is None else int(w.size)
+    rc = lib().orc_preprocess_u8(T, H, W, _ptr(x), _ptr(out), n, _ptr(w), int(bool(median)),
+                                 int(nthreads))
+    if rc != 0:
+        raise ValueError(f"orc_preprocess_u8 failed ({rc})")
     return out
 
 

@@ -25,6 +25,23 @@
  *     skips the median.
  *
  * Frames are dense T x H x W (frame-major), FP64.
+ *
+ * orc_preprocess_u8 is the same pipeline as the appendix runs it on 8-bit
+ * frames (its blur and median snippets read and write 8-bit images), with
+ * these readings:
+ *   - the blur is the appendix's two-dimensional one: for each pixel a
+ *     single-precision sum, started at 0 and taken over the window's rows
+ *     (outer) and columns (inner), of the 8-bit value times the window's
+ *     weight, each product and sum rounded to single precision (no fused
+ *     multiply-add);
+ *   - the window's weights are the products w_i * w_j of the normalised
+ *     one-dimensional weights above (the two-dimensional Gaussian density
+ *     factors into them), each product taken in double precision and rounded
+ *     once to single precision;
+ *   - the blurred value is written to the 8-bit image by dropping its fraction
+ *     (limited to [0, 255], where the conversion has no defined result);
+ *   - the median then sorts the nine 8-bit values of each clamped 3 x 3
+ *     neighbourhood of the blurred image and takes the middle one.
  */
 #include <math.h>
 #include <stdint.h>
@@ -120,6 +137,84 @@ int orc_preprocess(int64_t T, int64_t H, int64_t W, const double* in, double* ou
       }
     }
     free(hb);
+    free(gb);
+  }
+  return rc;
+}
+
+/* median of nine 8-bit values: insertion sort ascending, take the middle */
+static uint8_t pre_median9_u8(uint8_t v[9]) {
+  for (int i = 1; i < 9; ++i) {
+    const uint8_t x = v[i];
+    int j = i - 1;
+    while (j >= 0 && v[j] > x) {
+      v[j + 1] = v[j];
+      --j;
+    }
+    v[j + 1] = x;
+  }
+  return v[4];
+}
+
+int orc_preprocess_u8(int64_t T, int64_t H, int64_t W, const uint8_t* in, uint8_t* out, int32_t n,
+                      const double* w, int32_t median, int nthreads) {
+  if (T < 0 || H < 0 || W < 0 || (n != 0 && (n < 1 || n > 31 || (n % 2) == 0 || !w))) return -1;
+  if (T == 0 || H == 0 || W == 0) return 0;
+  if (!in || !out) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  const int64_t HW = H * W;
+  const int32_t r = n > 0 ? (n - 1) / 2 : 0;
+  /* the window's single-precision weights, row-major */
+  float w2[31 * 31];
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t j = 0; j < n; ++j) w2[i * n + j] = (float)(w[i] * w[j]);
+  int rc = 0;
+#pragma omp parallel
+  {
+    uint8_t* gb = (uint8_t*)malloc((size_t)HW);
+    if (!gb) {
+#pragma omp atomic write
+      rc = -1;
+    }
+#pragma omp for schedule(static)
+    for (int64_t t = 0; t < T; ++t) {
+      if (!gb) continue;
+      const uint8_t* x = in + t * HW;
+      if (n > 0) {
+        for (int64_t y = 0; y < H; ++y)
+          for (int64_t c = 0; c < W; ++c) {
+            float blur = 0.0f;
+            for (int32_t i = 0; i < n; ++i)
+              for (int32_t j = 0; j < n; ++j) {
+                const float pixel = (float)x[pre_clamp(y + i - r, H - 1) * W + pre_clamp(c + j - r, W - 1)];
+                const float prod = pixel * w2[i * n + j];
+                blur = blur + prod;
+              }
+            const float f = truncf(blur);
+            gb[y * W + c] = (uint8_t)(f < 0.0f ? 0.0f : (f > 255.0f ? 255.0f : f));
+          }
+      } else {
+        for (int64_t k = 0; k < HW; ++k) gb[k] = x[k];
+      }
+      uint8_t* o = out + t * HW;
+      if (median) {
+        for (int64_t y = 0; y < H; ++y)
+          for (int64_t c = 0; c < W; ++c) {
+            uint8_t v[9];
+            int k = 0;
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx)
+                v[k++] = gb[pre_clamp(y + dy, H - 1) * W + pre_clamp(c + dx, W - 1)];
+            o[y * W + c] = pre_median9_u8(v);
+          }
+      } else {
+        for (int64_t k = 0; k < HW; ++k) o[k] = gb[k];
+      }
+    }
     free(gb);
   }
   return rc;

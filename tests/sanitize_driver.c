@@ -10,6 +10,8 @@
 int orc_gauss_weights(int32_t n, double sigma, double* w);
 int orc_preprocess(int64_t T, int64_t H, int64_t W, const double* in, double* out, int32_t n,
                    const double* w, int32_t median, int nthreads);
+int orc_preprocess_u8(int64_t T, int64_t H, int64_t W, const uint8_t* in, uint8_t* out,
+                      int32_t n, const double* w, int32_t median, int nthreads);
 
 static uint64_t rng_state = 0x9E3779B97F4A7C15ull;
 static double urand(void) { /* xorshift64*, uniform in [-1, 1) */
@@ -99,6 +101,14 @@ static int run(int64_t T, int64_t H, int64_t W, int32_t rule, int32_t mrule) {
   CHECK(orc_preprocess(T, H, W, x, f1, 0, NULL, 1, 0));
   CHECK(orc_gauss_weights(7, 2.0, w));
   CHECK(orc_preprocess(T, H, W, x, f1, 7, w, 0, 0));
+  {
+    uint8_t* pu = (uint8_t*)malloc((size_t)(T * H * W) + 1);
+    CHECK(orc_preprocess_u8(T, H, W, u8x, pu, 7, w, 1, 0));
+    CHECK(orc_gauss_weights(3, 0.8, w));
+    CHECK(orc_preprocess_u8(T, H, W, u8x, pu, 3, w, 0, 0));
+    CHECK(orc_preprocess_u8(T, H, W, u8x, pu, 0, NULL, 1, 0));
+    free(pu);
+  }
   free(x); free(mA); free(vA); free(mC); free(vC); free(aA); free(aC);
   free(m0); free(v0); free(c0); free(w0); free(a0); free(b0);
   free(masks); free(codes); free(bg); free(marg); free(gbg); free(gst); free(gx); free(gs0);

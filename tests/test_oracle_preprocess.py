@@ -106,3 +106,99 @@ def test_single_pixel_and_thin_frames():
     # one row: the column pass sees the same row five times
     ref = scipy_ndimage.correlate1d(row[0], w, axis=1, mode="nearest")
     assert np.max(np.abs(out[0] - ref)) <= 1e-15
+
+
+# ------------------------------------------------ the appendix's 8-bit pipeline
+def _exact_blur_u8(x, w):
+    """The 2-D blur of one uint8 frame in exact rational arithmetic with the
+    single-precision window weights float(w_i * w_j) (exact binary fractions),
+    borders clamped to the last row and column: the real value the
+    single-precision sum approximates."""
+    from fractions import Fraction
+    n = w.size
+    r = (n - 1) // 2
+    H, W = x.shape
+    w2 = [[Fraction(float(np.float32(w[i] * w[j]))) for j in range(n)] for i in range(n)]
+    out = np.empty((H, W), dtype=object)
+    for y in range(H):
+        for c in range(W):
+            acc = Fraction(0)
+            for i in range(n):
+                for j in range(n):
+                    yy = min(max(y + i - r, 0), H - 1)
+                    xx = min(max(c + j - r, 0), W - 1)
+                    acc += int(x[yy, xx]) * w2[i][j]
+            out[y, c] = acc
+    return out
+
+
+@pytest.mark.parametrize("n,sigma,seed", [(3, 0.8, 1), (5, 1.0, 2), (7, 1.5, 3)])
+def test_u8_blur_is_the_truncated_exact_sum(n, sigma, seed):
+    """Each 8-bit blurred value is the integer part of the exact 2-D weighted
+    sum, except where that sum lies within the single-precision rounding of
+    25-49 terms of an integer (there it may be one less or one more)."""
+    w = oracle.gauss_weights(n, sigma)
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, 256, size=(1, 9, 11), dtype=np.uint8)
+    got = oracle.preprocess_u8(x, w, median=False)[0].astype(int)
+    ex = _exact_blur_u8(x[0], w)
+    near = 0
+    for y in range(x.shape[1]):
+        for c in range(x.shape[2]):
+            e = ex[y, c]
+            fl = e.numerator // e.denominator
+            if abs(float(e - round(e))) < 1e-3:   # float rounding may cross the integer
+                near += 1
+                assert abs(got[y, c] - float(e)) < 1.0
+            else:
+                assert got[y, c] == fl, (y, c, float(e))
+    assert near < x.size // 4
+
+
+def test_u8_impulse_response_drops_the_fraction():
+    """A single bright pixel: each blurred value is the integer part of
+    255 * float(w_i * w_j) at the mirrored offset (not its rounded value)."""
+    w = oracle.gauss_weights(5, 1.0)
+    x = np.zeros((1, 11, 13), dtype=np.uint8)
+    x[0, 5, 6] = 255
+    got = oracle.preprocess_u8(x, w, median=False)[0]
+    want = np.zeros((11, 13), dtype=np.uint8)
+    for i in range(5):
+        for j in range(5):
+            v = 255.0 * float(np.float32(w[i] * w[j]))
+            want[5 + 2 - i, 6 + 2 - j] = int(np.floor(v))
+    assert np.array_equal(got, want)
+    # the rounding rule matters here: some products have a fraction >= 1/2
+    fr = [255.0 * float(np.float32(w[i] * w[j])) % 1 for i in range(5) for j in range(5)]
+    assert max(fr) >= 0.5
+
+
+def test_u8_median_brute_force_and_identity():
+    """Without a blur the 8-bit pipeline is the 3 x 3 median of the frame,
+    checked against numpy's median of each clamped neighbourhood; without
+    either it is the identity."""
+    rng = np.random.default_rng(7)
+    x = rng.integers(0, 256, size=(2, 7, 9), dtype=np.uint8)
+    got = oracle.preprocess_u8(x, None, median=True)
+    for t in range(2):
+        for y in range(7):
+            for c in range(9):
+                nb = [x[t, min(max(y + dy, 0), 6), min(max(c + dx, 0), 8)]
+                      for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+                assert got[t, y, c] == int(np.median(nb))
+    assert np.array_equal(oracle.preprocess_u8(x, None, median=False), x)
+
+
+def test_u8_blur_then_median_and_constant_frames():
+    """The median runs on the blurred 8-bit image; a constant frame c blurs to
+    c or c - 1 (the single-precision weights sum to 1 within a few ulp) and
+    stays constant."""
+    w = oracle.gauss_weights(5, 1.0)
+    rng = np.random.default_rng(8)
+    x = rng.integers(0, 256, size=(1, 8, 10), dtype=np.uint8)
+    b = oracle.preprocess_u8(x, w, median=False)
+    assert np.array_equal(oracle.preprocess_u8(x, w, median=True),
+                          oracle.preprocess_u8(b, None, median=True))
+    for c in (0, 1, 17, 128, 254, 255):
+        out = oracle.preprocess_u8(np.full((1, 6, 7), c, np.uint8), w, median=True)
+        assert out.min() == out.max() and out[0, 0, 0] in (c, max(c - 1, 0))
