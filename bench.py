@@ -84,6 +84,7 @@ OPS_PRE = 22 + 18 + 14   # + 5-tap row and column passes (9 each) + 3 x 3 median
 OPS_WARP = 22 + 32 + 6 + 28 + 4   # + homography (2 divisions) + weights + 4 bilinear planes + nearest
 OPS_GRID4 = 10 + 22 / 16   # per pixel: block sum 1, V 3, mask 6; the step once per 16 pixels
 OPS_U8 = 22 + 12    # + the 8-bit storage rule on 4 values
+OPS_PRE_U8 = OPS_U8 + 50 + 14 + 2   # + the 5 x 5 window (25 products, 25 sums), median, store rule
 
 
 # the sources a kernel is compiled from: its translation unit and the headers
@@ -378,7 +379,8 @@ def leg_video(args, dsgm, sdev, torch):
 def leg_filtered(args, dsgm, sdev, torch):
     """The forward with the paper's preprocessing fused in (5-tap Gaussian,
     sigma 1, then the 3x3 median): the main workload's frames and state (FP64),
-    and BF16 frames with FP32 state."""
+    BF16 frames with FP32 state, and the appendix's 8-bit pipeline (U8 frames
+    and state, its two-dimensional single-precision blur)."""
     T, H, W, seed = 500, 1920, 2560, 1
     p = dsgm.dsgm_params_default(2.0)
     filt = dsgm.gauss_filter(5, 1.0, True)
@@ -406,6 +408,23 @@ def leg_filtered(args, dsgm, sdev, torch):
             out[name]["error_vs_fp64"] = err
         del fr, st, st0, masks
         torch.cuda.empty_cache()
+    # the appendix's pipeline on 8-bit images: its two-dimensional single-
+    # precision blur written back to 8 bits, the median of the 8-bit image and
+    # the 8-bit as-run update, on the structured video at 8-bit levels
+    fr = (sdev.video(seed, T, H, W, torch.float32) * 128 + 128).to(torch.uint8)
+    p8 = dsgm.dsgm_params_default(255.0, dsgm.MASK_PRINTED)
+    p8.weight_rule = dsgm.WEIGHT_APPENDIX
+    st = dsgm.State.empty(H, W, torch.uint8)
+    dsgm.dsgm_state_init_from_frame(fr[0], st, p8)
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    ms, kk = timed(lambda: dsgm.dsgm_forward_filtered(fr, st, p8, filt, masks), steps, 1, stream)
+    out["u8_as_run"] = {"workload": "structured video at 8-bit levels, 8-bit state, the appendix's "
+                                    "weights and printed mask rule",
+                        "elements_per_s": round(elems / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                        "roofline": roof(elems * 2 + px * 12, float(sum(kk) / len(kk)), elems,
+                                         OPS_PRE_U8)}
+    del fr, st, masks
+    torch.cuda.empty_cache()
     return out
 
 

@@ -280,6 +280,17 @@ int dsgm_gauss_weights(int32_t n, double sigma, double* weights /* host, n */);
  * host struct; n > 7 returns DSGM_E_UNSUPPORTED.  With ACC_F64 the results are
  * bit-identical to a scalar FP64 evaluation of the blur sums, the median and
  * the update in the stated order.
+ *
+ * U8 frames with U8 state run the pipeline as the appendix runs it on 8-bit
+ * images (its blur, median and update snippets): the blur is two-dimensional,
+ * a single-precision sum over the window's rows (outer) and columns (inner) of
+ * each byte times the weight float(weights[i] * weights[j]) (product in
+ * double, rounded once), every product and sum rounded, written back to 8
+ * bits by dropping the fraction (limited to 255); the median takes the nine
+ * blurred bytes of each clamped 3 x 3 neighbourhood; the update is the 8-bit
+ * as-run model of dsgm_forward.  `filtered` (optional) receives the median's
+ * bytes; bg must be NULL (DSGM_E_UNSUPPORTED).  Bit-identical to a scalar
+ * evaluation in that order.
  */
 int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape shape,
                           dsgm_acc acc, const dsgm_params* params /* host */,

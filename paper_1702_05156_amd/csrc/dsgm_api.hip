@@ -651,8 +651,16 @@ int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape
                           dsgm_state* state, uint8_t* masks, void* bg, void* filtered,
                           uint8_t* codes, hipStream_t stream) {
   int rc;
-  if ((rc = check_types(in_dtype, acc))) return rc;
+  // the 8-bit pair runs the appendix's 8-bit preprocessing and update
+  const bool as_run = in_dtype == DSGM_IN_U8 || acc == DSGM_ACC_U8;
+  if (as_run) {
+    if (in_dtype != DSGM_IN_U8 || acc != DSGM_ACC_U8)
+      return fail(DSGM_E_DTYPE, "U8 frames and U8 state go together");
+  } else if ((rc = check_types(in_dtype, acc))) {
+    return rc;
+  }
   if ((rc = check_params(params))) return rc;
+  if (as_run && bg) return fail(DSGM_E_UNSUPPORTED, "the 8-bit as-run model has no bg output");
   if (!filter) return fail(DSGM_E_ARG, "filter is NULL");
   if (filter->n < 0 || (filter->n > 0 && filter->n % 2 == 0))
     return fail(DSGM_E_ARG, "blur taps n = %d (0 or odd)", filter->n);
@@ -663,7 +671,7 @@ int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape
     return fail(DSGM_E_ARG, "median = %d (0 or 1)", filter->median);
   for (int i = 0; i < filter->n; ++i)
     if (!std::isfinite(filter->weights[i])) return fail(DSGM_E_ARG, "blur weight %d not finite", i);
-  const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = io_size(acc);
+  const size_t ie = in_size(in_dtype), ae = acc_size(acc), oe = as_run ? 1 : io_size(acc);
   if ((rc = check_shape(shape, ie > oe ? ie : oe))) return rc;
   if (!state) return fail(DSGM_E_ARG, "state is NULL");
   if (shape.H * shape.W == 0 || shape.T == 0) return ok();
@@ -710,7 +718,7 @@ int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape
     return fail(DSGM_E_SHAPE, "too many tiles");
   a.theta_s = params->theta_s;
   a.theta_d = params->theta_d;
-  a.var_init = params->var_init;
+  a.var_init = as_run ? stored_u8(params->var_init) : params->var_init;
   a.var_floor = params->var_floor;
   a.mask_floor = params->mask_floor;
   a.age_max = params->age_max;
@@ -718,7 +726,8 @@ int dsgm_forward_filtered(const void* frames, dsgm_in_dtype in_dtype, dsgm_shape
   a.mask_rule = params->mask_rule;
   for (int i = 0; i < filter->n; ++i) a.w[i] = filter->weights[i];
   const int rg = filter->n > 0 ? (filter->n - 1) / 2 : 0;  // n = 1 (weight 1) is no blur
-  hipError_t e = dsgm::launch_pre(a, in_dtype, acc, rg, filter->median != 0, stream);
+  hipError_t e = as_run ? dsgm::launch_pre_u8(a, rg, filter->median != 0, stream)
+                        : dsgm::launch_pre(a, in_dtype, acc, rg, filter->median != 0, stream);
   if (e != hipSuccess) return hip_fail(e, "dsgm_forward_filtered launch");
   return ok();
 }

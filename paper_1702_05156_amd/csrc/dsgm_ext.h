@@ -36,6 +36,9 @@ struct PreArgs {
 // rg: blur radius 0..3 (0: no blur); median: 3 x 3 median after the blur
 hipError_t launch_pre(const PreArgs& a, int in_dtype, int acc, int rg, bool median,
                       hipStream_t stream);
+// the 8-bit form (dsgm_u8.hip): U8 frames and state, var_init already stored,
+// the appendix's two-dimensional single-precision blur written back to 8 bits
+hipError_t launch_pre_u8(const PreArgs& a, int rg, bool median, hipStream_t stream);
 
 // Arguments of one frame of the update on the motion-compensated model
 // (dsgm_warp.hip).

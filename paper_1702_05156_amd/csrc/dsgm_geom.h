@@ -127,6 +127,7 @@ struct Geo {
   static constexpr int LOADS = (RAW_N + NT - 1) / NT;  // raw elements per lane
   static constexpr int ROW_IT = (HB_N / 2 + NT - 1) / NT;  // row-pass output pairs per lane
   static constexpr int COL_IT = (GB_N / 2 + NT - 1) / NT;  // column-pass output pairs per lane
+  static constexpr int GB_IT = (GB_N + NT - 1) / NT;  // 2-D blur cells per lane (8-bit form)
 
   // the raw cell a lane stages in its l-th load, and whether it has one
   DSGM_HD static int raw_cell(int tid, int l) { return tid + l * NT; }
@@ -153,6 +154,16 @@ struct Geo {
   DSGM_HD static int col_pair(int tid, int it) { return tid + it * NT; }
   DSGM_HD static bool col_active(int tid, int it) {
     return it + 1 < COL_IT || col_pair(tid, it) < GB_N / 2;
+  }
+  // the it-th cell of the two-dimensional blur (the 8-bit form): GB cell
+  // `cell` from the (2*RG + 1) x (2*RG + 1) raw window whose top-left cell is
+  // blur_window(cell) (GB cell (r, c) is frame pixel (y0 - RM + r, x0 - RM + c),
+  // whose window starts at raw cell (r, c))
+  DSGM_HD static int gb_cell(int tid, int it) { return tid + it * NT; }
+  DSGM_HD static bool gb_active(int tid, int it) { return it + 1 < GB_IT || gb_cell(tid, it) < GB_N; }
+  DSGM_HD static int blur_window(int cell) {
+    const int r = cell / GB_W, c = cell - r * GB_W;
+    return r * RAW_W + c;
   }
   // the lane's row and first column in the tile
   DSGM_HD static int lane_row(int tid) { return tid / (TW / PX); }

@@ -259,6 +259,227 @@ __global__ void __launch_bounds__(256) u8_init_kernel(const FwdArgs a) {
   a.age_c[i] = 1;
 }
 
+// The appendix's preprocessing as it runs on 8-bit frames, fused into the
+// 8-bit update (one pass over the sequence, like pre_kernel): a workgroup owns
+// a 16 x 64 tile for all frames, each lane four adjacent pixels of one row
+// with their models in registers.  Per frame it stages the tile's raw bytes
+// plus a halo of RG + 1 rows and columns in LDS (indices clamped to the frame),
+// computes every blurred byte of the tile and of the median's halo with the
+// two-dimensional single-precision sum of the appendix's blur (window rows
+// outer, columns inner, weights float(w_i * w_j), every product and sum
+// rounded, no fused multiply-add), drops its fraction (limited to 255), takes
+// each pixel's median of the nine blurred bytes around it and runs the 8-bit
+// update on it.  Two barriers per frame: after the raw bytes are staged and
+// after the blurred bytes are written; the next frame's bytes are loaded into
+// registers while the current one is filtered.  All tile cell indices come
+// from geom::pre::Geo.
+template <int RG, bool MED, bool PRINTED>
+__global__ void __launch_bounds__(256) pre_u8_kernel(const PreArgs a) {
+  using G = geom::pre::Geo<RG, MED>;
+  constexpr int PX = geom::pre::PX, TH = geom::pre::TH, TW = geom::pre::TW;
+  constexpr int N = 2 * RG + 1;  // taps per window row
+  __shared__ float buf_raw[G::RAW_N];
+  __shared__ float buf_gb[RG > 0 ? G::GB_N : 1];
+  __shared__ TableEntry<double> tbl[TABLE_SIZE];
+  fill_table<double>(tbl, a.weight_rule, a.age_max, a.var_init);  // var_init already stored
+  const StepConsts<double> k =
+      make_consts<double>(a.theta_s, a.theta_d, a.var_init, a.var_floor, a.mask_floor);
+  float w2[N * N];  // the window's weights, row-major, rounded once
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) w2[i * N + j] = float(a.w[i] * a.w[j]);
+
+  const int64_t tile = tile_of(blockIdx.x, gridDim.x);
+  const int64_t y0 = (tile / a.tiles_x) * TH, x0 = (tile % a.tiles_x) * TW;
+  const int tid = threadIdx.x;
+  const int ty = G::lane_row(tid), tx = G::lane_col(tid);
+  const int64_t gy = y0 + ty;
+
+  uint32_t roff[G::LOADS];  // frame offsets of this lane's raw cells (fixed per frame)
+#pragma unroll
+  for (int l = 0; l < G::LOADS; ++l) {
+    const int i = G::raw_cell(tid, l);
+    roff[l] = i < G::RAW_N ? uint32_t(G::raw_source(i, y0, x0, a.H, a.W, a.row_stride)) : 0u;
+  }
+  int gr[3], gc[PX + 2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) gr[d] = G::med_row(gy, d, y0, a.H);
+#pragma unroll
+  for (int d = 0; d < PX + 2; ++d) gc[d] = G::med_col(x0 + tx, d, x0, a.W);
+
+  bool valid[PX];
+  bool all_valid = gy < a.H;
+#pragma unroll
+  for (int q = 0; q < PX; ++q) {
+    valid[q] = gy < a.H && x0 + tx + q < a.W;
+    all_valid = all_valid && valid[q];
+  }
+  const int64_t pix = gy * a.W + x0 + tx;
+  const int64_t foff = gy * a.row_stride + x0 + tx;
+  const bool vec_ok = all_valid && (a.row_stride % PX) == 0 && (a.frame_stride % PX) == 0 &&
+                      (a.W % PX) == 0;
+
+  const uint8_t* const planes_in[4] = {static_cast<const uint8_t*>(a.mean_a),
+                                       static_cast<const uint8_t*>(a.var_a),
+                                       static_cast<const uint8_t*>(a.mean_c),
+                                       static_cast<const uint8_t*>(a.var_c)};
+  Model<double> s[PX];
+#pragma unroll
+  for (int q = 0; q < PX; ++q) {
+    if (valid[q]) {
+      s[q].mA = double(planes_in[0][pix + q]);
+      s[q].vA = double(planes_in[1][pix + q]);
+      s[q].mC = double(planes_in[2][pix + q]);
+      s[q].vC = double(planes_in[3][pix + q]);
+      s[q].aA = a.age_a[pix + q];
+      s[q].aC = a.age_c[pix + q];
+    } else {
+      s[q].mA = s[q].vA = s[q].mC = s[q].vC = 0.0;
+      s[q].aA = s[q].aC = 1;
+    }
+  }
+
+  const uint8_t* frames = static_cast<const uint8_t*>(a.frames);
+  uint8_t nxt[G::LOADS];
+  auto load_frame = [&](int64_t t) {
+    const uint8_t* f = frames + t * a.frame_stride;
+#pragma unroll
+    for (int l = 0; l < G::LOADS; ++l)
+      if (G::raw_active(tid, l)) nxt[l] = f[roff[l]];
+  };
+  if (a.T > 0) load_frame(0);
+
+  for (int64_t t = 0; t < a.T; ++t) {
+    // 1. stage the raw bytes, then start loading the next frame's
+#pragma unroll
+    for (int l = 0; l < G::LOADS; ++l)
+      if (G::raw_active(tid, l)) buf_raw[G::raw_cell(tid, l)] = float(nxt[l]);
+    __syncthreads();
+    if (t + 1 < a.T) load_frame(t + 1);
+
+    const float* gbp;
+    if constexpr (RG > 0) {
+      // 2. the blurred bytes of the tile and the median's halo
+#pragma unroll
+      for (int it = 0; it < G::GB_IT; ++it) {
+        if (G::gb_active(tid, it)) {
+          const int cell = G::gb_cell(tid, it);
+          const float* win = buf_raw + G::blur_window(cell);
+          float blur = 0.0f;
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+              const float prod = win[i * G::RAW_W + j] * w2[i * N + j];
+              blur = blur + prod;
+            }
+          buf_gb[cell] = __builtin_fminf(255.0f, __builtin_fmaxf(0.0f, __builtin_truncf(blur)));
+        }
+      }
+      __syncthreads();
+      gbp = buf_gb;
+    } else {
+      gbp = buf_raw;  // no blur: the raw bytes are the blurred ones (R = RM)
+    }
+    constexpr int GW = RG > 0 ? G::GB_W : G::RAW_W;
+
+    // 3. each pixel's median of the nine blurred bytes (exact in single
+    // precision: the values are integers), then the 8-bit update
+    double xs[PX];
+    if constexpr (MED) {
+      float lo[PX + 2], md[PX + 2], hi[PX + 2];
+#pragma unroll
+      for (int d = 0; d < PX + 2; ++d) {
+        const float p0 = gbp[gr[0] * GW + gc[d]];
+        const float p1 = gbp[gr[1] * GW + gc[d]];
+        const float p2 = gbp[gr[2] * GW + gc[d]];
+        const float l01 = __builtin_fminf(p0, p1), h01 = __builtin_fmaxf(p0, p1);
+        lo[d] = __builtin_fminf(l01, p2);
+        const float h = __builtin_fmaxf(l01, p2);
+        hi[d] = __builtin_fmaxf(h01, h);
+        md[d] = __builtin_fminf(h01, h);
+      }
+#pragma unroll
+      for (int q = 0; q < PX; ++q) {
+        const float a0 = __builtin_fmaxf(__builtin_fmaxf(lo[q], lo[q + 1]), lo[q + 2]);
+        const float b0 = __builtin_fmaxf(__builtin_fminf(md[q], md[q + 1]),
+                                         __builtin_fminf(__builtin_fmaxf(md[q], md[q + 1]), md[q + 2]));
+        const float c0 = __builtin_fminf(__builtin_fminf(hi[q], hi[q + 1]), hi[q + 2]);
+        xs[q] = double(__builtin_fmaxf(__builtin_fminf(a0, b0),
+                                       __builtin_fminf(__builtin_fmaxf(a0, b0), c0)));
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < PX; ++q) xs[q] = double(gbp[gr[1] * GW + gc[q + 1]]);
+    }
+
+    StepRecord<double> r[PX];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+      r[q] = step_core<double>(s[q], xs[q], k, tbl);
+      s[q].mA = stored(s[q].mA);
+      s[q].vA = stored(s[q].vA);
+      s[q].mC = stored(s[q].mC);
+      s[q].vC = stored(s[q].vC);
+      any |= r[q].swap;
+    }
+    if (any_lane(any)) {
+#pragma unroll
+      for (int q = 0; q < PX; ++q) apply_swap<double>(s[q], xs[q], k, r[q].swap);
+    }
+    Vec<uint8_t, PX> mk, cd, fv;
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+      r[q].fg = fg_of<double, PRINTED>(s[q], xs[q], k);
+      mk.v[q] = r[q].fg ? uint8_t(255) : uint8_t(0);
+      cd.v[q] = uint8_t(code_of<double>(r[q]));
+      fv.v[q] = uint8_t(xs[q]);
+    }
+    uint8_t* const filt = static_cast<uint8_t*>(a.filtered);
+    const int64_t o = t * a.frame_stride + foff;
+    if (vec_ok) {
+      *reinterpret_cast<Vec<uint8_t, PX>*>(a.masks + o) = mk;
+      if (filt) *reinterpret_cast<Vec<uint8_t, PX>*>(filt + o) = fv;
+      if (a.codes) *reinterpret_cast<Vec<uint8_t, PX>*>(a.codes + o) = cd;
+    } else {
+#pragma unroll
+      for (int q = 0; q < PX; ++q) {
+        if (!valid[q]) continue;
+        a.masks[o + q] = mk.v[q];
+        if (filt) filt[o + q] = fv.v[q];
+        if (a.codes) a.codes[o + q] = cd.v[q];
+      }
+    }
+    if constexpr (RG == 0) __syncthreads();  // the next frame overwrites the raw bytes
+  }
+
+#pragma unroll
+  for (int q = 0; q < PX; ++q) {
+    if (!valid[q]) continue;
+    static_cast<uint8_t*>(a.mean_a)[pix + q] = uint8_t(s[q].mA);
+    static_cast<uint8_t*>(a.var_a)[pix + q] = uint8_t(s[q].vA);
+    static_cast<uint8_t*>(a.mean_c)[pix + q] = uint8_t(s[q].mC);
+    static_cast<uint8_t*>(a.var_c)[pix + q] = uint8_t(s[q].vC);
+    a.age_a[pix + q] = uint8_t(s[q].aA);
+    a.age_c[pix + q] = uint8_t(s[q].aC);
+  }
+}
+
+template <bool MED, bool PRINTED>
+hipError_t launch_pre_rg(const PreArgs& a, int rg, hipStream_t stream) {
+  const dim3 grid{uint32_t(a.tiles_x * a.tiles_y), 1, 1}, block{geom::pre::NT, 1, 1};
+  switch (rg) {
+    case 0: hipLaunchKernelGGL((pre_u8_kernel<0, MED, PRINTED>), grid, block, 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((pre_u8_kernel<1, MED, PRINTED>), grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((pre_u8_kernel<2, MED, PRINTED>), grid, block, 0, stream, a); break;
+    case 3: hipLaunchKernelGGL((pre_u8_kernel<3, MED, PRINTED>), grid, block, 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace u8
 
 hipError_t launch_fwd_u8(const FwdArgs& a, int P, int flags, int block, hipStream_t stream) {
@@ -267,6 +488,15 @@ hipError_t launch_fwd_u8(const FwdArgs& a, int P, int flags, int block, hipStrea
   if (P == 2) return u8::launch_p<2>(a, flags, block, stream);
   if (P == 1) return u8::launch_p<1>(a, flags, block, stream);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_pre_u8(const PreArgs& a, int rg, bool median, hipStream_t stream) {
+  const bool printed = a.mask_rule != 0;
+  if (median)
+    return printed ? u8::launch_pre_rg<true, true>(a, rg, stream)
+                   : u8::launch_pre_rg<true, false>(a, rg, stream);
+  return printed ? u8::launch_pre_rg<false, true>(a, rg, stream)
+                 : u8::launch_pre_rg<false, false>(a, rg, stream);
 }
 
 hipError_t launch_init_u8(const FwdArgs& a, hipStream_t stream) {

@@ -326,6 +326,19 @@ static void check_pre_rg(const Shape& s) {
           CHECK(w0 / G::RAW_W == (2 * pi) / G::HB_W && w0 % G::RAW_W == (2 * pi) % G::HB_W,
                 "row window not aligned with its outputs");
         }
+        // the two-dimensional blur of the 8-bit form: every GB cell's window
+        // lies in the raw tile, centred on the cell's frame pixel
+        for (int it = 0; it < G::GB_IT; ++it) {
+          if (!G::gb_active(tid, it)) continue;
+          const int cell = G::gb_cell(tid, it), win = G::blur_window(cell);
+          CHECK(cell >= 0 && cell < G::GB_N, "2-D blur cell %d", cell);
+          const int wr = win / G::RAW_W, wc = win % G::RAW_W;
+          CHECK(wr + 2 * RG < G::RAW_H && wc + 2 * RG < G::RAW_W, "2-D window (%d, %d)", wr, wc);
+          // frame offsets from the tile origin: the window's centre raw cell
+          // (wr + RG - R) and the cell's pixel (its GB index - RM) coincide
+          CHECK(wr + RG - G::R == cell / G::GB_W - G::RM && wc + RG - G::R == cell % G::GB_W - G::RM,
+                "2-D window not centred on its cell");
+        }
         for (int it = 0; it < G::COL_IT; ++it) {
           if (!G::col_active(tid, it)) continue;
           const int pi = G::col_pair(tid, it);

@@ -346,6 +346,23 @@ def test_empty_problems_of_the_extensions_need_no_gpu():
     rc = lib.dsgm_backward(1 << 20, 3, dsgm.Shape(2, 8, 8, 8, 64), 3, ctypes.byref(p8), None, 0,
                            1, None, None, 1 << 20, None, None, None, 0, None)
     assert rc == -3
+    # the 8-bit preprocessing pipeline: U8 frames with U8 state only, no bg
+    f = dsgm.gauss_filter(5, 1.0, True)
+    rc = lib.dsgm_forward_filtered(1 << 20, 3, dsgm.Shape(2, 8, 8, 8, 64), 1, ctypes.byref(p8),
+                                   ctypes.byref(f), ctypes.byref(st), 1 << 20, None, None, None,
+                                   None)
+    assert rc == -3
+    rc = lib.dsgm_forward_filtered(1 << 20, 1, dsgm.Shape(2, 8, 8, 8, 64), 3, ctypes.byref(p8),
+                                   ctypes.byref(f), ctypes.byref(st), 1 << 20, None, None, None,
+                                   None)
+    assert rc == -3
+    rc = lib.dsgm_forward_filtered(1 << 20, 3, dsgm.Shape(2, 8, 8, 8, 64), 3, ctypes.byref(p8),
+                                   ctypes.byref(f), ctypes.byref(st), 1 << 20, 1 << 21, None, None,
+                                   None)
+    assert rc == -7
+    rc = lib.dsgm_forward_filtered(None, 3, dsgm.Shape(0, 8, 8, 8, 64), 3, ctypes.byref(p8),
+                                   ctypes.byref(f), ctypes.byref(st), None, None, None, None, None)
+    assert rc == 0
 
 
 def test_autotune_arguments_rejected_before_any_hip_call():

@@ -165,3 +165,140 @@ def test_full_size_filtered_f64_sampled_bit_exact():
     for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
         G.assert_bit_exact(k, hs[k][pix], ref[k])
     del fr, masks
+
+
+# ---------------------------------------- the appendix's 8-bit pipeline, end to end
+def _u8_case(seed, T, H, W):
+    x = (synth.video_levels(seed, T, H, W) + 128).astype(np.uint8).reshape(T, H, W)
+    rng = np.random.default_rng(seed)
+    st = {k: rng.integers(0, 256, H * W).astype(np.uint8) for k in ("mean_a", "var_a", "mean_c", "var_c")}
+    st["age_a"] = rng.integers(1, 31, H * W).astype(np.uint8)
+    st["age_c"] = rng.integers(1, 31, H * W).astype(np.uint8)
+    return x, st
+
+
+def _u8_state(st, H, W):
+    t = lambda k: torch.as_tensor(st[k].reshape(H, W), device="cuda").contiguous()
+    return dsgm.State(t("mean_a"), t("var_a"), t("mean_c"), t("var_c"), t("age_a"), t("age_c"))
+
+
+def _u8_check(out, dst, x, st, p, n, median, sigma=1.0):
+    T = x.shape[0]
+    w = oracle.gauss_weights(n, sigma) if n > 1 else None
+    xf = oracle.preprocess_u8(x, w, median=bool(median))
+    G.assert_bit_exact("filtered", G.flat(out["filtered"]).astype(np.int64),
+                       xf.reshape(T, -1).astype(np.int64))
+    ref = oracle.forward_u8(xf.reshape(T, -1), st, G.oracle_params(p))
+    G.assert_bit_exact("codes", G.flat(out["codes"]).astype(np.int64), ref["codes"].astype(np.int64))
+    G.assert_bit_exact("masks", G.flat(out["masks"]).astype(np.int64), ref["masks"].astype(np.int64))
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        got = getattr(dst, k).cpu().numpy().ravel()
+        G.assert_bit_exact(k, got.astype(np.int64), ref[k].astype(np.int64))
+
+
+@pytest.mark.parametrize("n,median", [(5, 1), (3, 1), (7, 1), (5, 0), (0, 1), (0, 0), (1, 1)])
+def test_u8_filtered_pipeline_bit_exact(n, median):
+    """U8 frames and state: the appendix's two-dimensional single-precision
+    blur written back to 8 bits, the 3 x 3 median of the 8-bit image and the
+    8-bit as-run update, all integer outputs identical to the oracle's."""
+    T, H, W = 23, 37, 150   # several tiles, ragged in both directions
+    x, st = _u8_case(51, T, H, W)
+    p = dsgm.dsgm_params_default(255.0)
+    filt = dsgm.gauss_filter(n, 1.0, median) if n else dsgm.gauss_filter(0, 1.0, median)
+    dst = _u8_state(st, H, W)
+    out = dsgm.forward_filtered(torch.as_tensor(x, device="cuda"), dst, p, filt, filtered=True,
+                                codes=True)
+    torch.cuda.synchronize()
+    _u8_check(out, dst, x, st, p, n, median)
+
+
+@pytest.mark.parametrize("wr,mr", [(1, 1), (1, 0), (0, 1)])
+def test_u8_filtered_other_rules_and_sigma(wr, mr):
+    p = dsgm.dsgm_params_default(255.0, mr)
+    p.weight_rule = wr
+    T, H, W = 19, 21, 70
+    x, st = _u8_case(52 + wr + 2 * mr, T, H, W)
+    filt = dsgm.gauss_filter(5, 1.7, True)
+    dst = _u8_state(st, H, W)
+    out = dsgm.forward_filtered(torch.as_tensor(x, device="cuda"), dst, p, filt, filtered=True,
+                                codes=True)
+    torch.cuda.synchronize()
+    _u8_check(out, dst, x, st, p, 5, 1, sigma=1.7)
+
+
+@pytest.mark.parametrize("T,H,W", [(3, 1, 1), (4, 1, 70), (4, 70, 1), (5, 16, 64), (2, 17, 65),
+                                   (1, 2, 3)])
+def test_u8_filtered_edge_shapes(T, H, W):
+    x, st = _u8_case(53, T, H, W)
+    p = dsgm.dsgm_params_default(255.0)
+    filt = dsgm.gauss_filter(5, 1.0, True)
+    dst = _u8_state(st, H, W)
+    out = dsgm.forward_filtered(torch.as_tensor(x, device="cuda"), dst, p, filt, filtered=True,
+                                codes=True)
+    torch.cuda.synchronize()
+    _u8_check(out, dst, x, st, p, 5, 1)
+
+
+def test_u8_filtered_strided_frames_and_rejections():
+    """A padded view of the frames (scalar stores), and the argument checks of
+    the 8-bit pairing."""
+    T, H, W = 9, 20, 70
+    x, st = _u8_case(54, T, H, W)
+    big = torch.zeros((T, H + 3, W + 5), dtype=torch.uint8, device="cuda")
+    big[:, :H, :W] = torch.as_tensor(x, device="cuda")
+    fr = big[:, :H, :W]
+    p = dsgm.dsgm_params_default(255.0)
+    filt = dsgm.gauss_filter(3, 0.8, True)
+    dst = _u8_state(st, H, W)
+    out = dsgm.forward_filtered(fr, dst, p, filt, filtered=True, codes=True)
+    torch.cuda.synchronize()
+    _u8_check(out, dst, x, st, p, 3, 1, sigma=0.8)
+    with pytest.raises(dsgm.DSGMError) as e:      # no bg in the 8-bit model
+        dsgm.forward_filtered(fr, _u8_state(st, H, W), p, filt, bg=True)
+    assert e.value.status == -7
+    f32 = dsgm.State(*[torch.zeros((H, W), dtype=torch.float32, device="cuda") for _ in range(4)],
+                     *[torch.ones((H, W), dtype=torch.uint8, device="cuda") for _ in range(2)])
+    with pytest.raises(dsgm.DSGMError) as e:      # U8 frames need U8 state
+        dsgm.forward_filtered(fr, f32, p, filt, acc=dsgm.ACC_F32)
+    assert e.value.status == -3
+
+
+@pytest.mark.slow
+def test_full_size_u8_filtered_sampled_bit_exact():
+    """1920x2560x60 U8 frames of the structured video, 5-tap Gaussian and 3x3
+    median as the appendix runs them on 8-bit images, fused with the 8-bit
+    update.  A filtered pixel depends on the raw frame within 3 rows and
+    columns, so the oracle filters a 7x7 crop around each sampled pixel (cut at
+    the frame edges, where both clamp alike) and runs the update on its centre."""
+    T, H, W, seed = 60, 1920, 2560, 5
+    p = dsgm.dsgm_params_default(255.0)
+    filt = dsgm.gauss_filter(5, 1.0, True)
+    fr = (sdev.video(seed, T, H, W, torch.float32) * 128 + 128).to(torch.uint8)
+    rng = np.random.default_rng(12)
+    st = {k: rng.integers(0, 256, H * W).astype(np.uint8) for k in ("mean_a", "var_a", "mean_c", "var_c")}
+    st["age_a"] = rng.integers(1, 31, H * W).astype(np.uint8)
+    st["age_c"] = rng.integers(1, 31, H * W).astype(np.uint8)
+    dst = _u8_state(st, H, W)
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    dsgm.dsgm_forward_filtered(fr, dst, p, filt, masks)
+    torch.cuda.synchronize()
+    pix = np.unique(np.concatenate([rng.choice(H * W, 256, replace=False),
+                                    [0, 1, W - 1, W, H * W - W, H * W - 1, 2 * W + 2]]))
+    w = oracle.gauss_weights(5, 1.0)
+    xf = np.empty((T, pix.size), np.uint8)
+    for k, q in enumerate(pix):
+        y, x = divmod(int(q), W)
+        ys = np.arange(max(0, y - 3), min(H, y + 4))
+        xs = np.arange(max(0, x - 3), min(W, x + 4))
+        crop_pix = (ys[:, None] * W + xs[None, :]).ravel()
+        raw = (synth.video_levels(seed, T, H, W, pix=crop_pix) + 128).astype(np.uint8)
+        xf[:, k] = oracle.preprocess_u8(raw.reshape(T, ys.size, xs.size), w)[:, y - ys[0], x - xs[0]]
+    st0 = {k: v[pix] for k, v in st.items()}
+    ref = oracle.forward_u8(xf, st0, G.oracle_params(p), codes=False)
+    pix_t = torch.as_tensor(pix, device="cuda")
+    G.assert_bit_exact("masks", masks.view(T, H * W)[:, pix_t].cpu().numpy().astype(np.int64),
+                       ref["masks"].astype(np.int64))
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        got = getattr(dst, k).cpu().numpy().ravel()[pix]
+        G.assert_bit_exact(k, got.astype(np.int64), ref[k].astype(np.int64))
+    del fr, masks
