@@ -62,7 +62,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # VALU lane-ops/s, an FMA counted as one op.  FP64: the published 78.6 TFLOP/s
 # vector peak -> 39.3 T, i.e. 64 lanes per CU per clock at 2.4 GHz on 256 CUs.
 # FP32: the published 157.3 TFLOP/s vector peak -> 78.6 T.  That figure is
-# quoted for packed FP32, which this build does not emit; it is still the
+# quoted for packed FP32, which the library does not emit; it is still the
 # ceiling used, because 32-bit VALU instructions measurably retire faster than
 # 64 lanes per CU per clock here: the BF16/FP32 forward's counters give 39.3
 # VALU wavefront instructions x 64 lanes per element over 2.4576 G elements in
