@@ -78,8 +78,10 @@ typedef enum { DSGM_IN_F64 = 0, DSGM_IN_F32 = 1, DSGM_IN_BF16 = 2, DSGM_IN_U8 = 
  *             variances kept as uint8 planes, FP64 arithmetic, every stored
  *             value converted to an integer with its fraction dropped and
  *             limited to [0, 255] (var_init too); the tests, the swap and the
- *             mask see the stored values.  dsgm_forward (masks, codes) and
- *             dsgm_state_init_from_frame only; other calls return DSGM_E_DTYPE
+ *             mask see the stored values.  dsgm_forward (masks, codes),
+ *             dsgm_forward_filtered (the appendix's 8-bit preprocessing first)
+ *             and dsgm_state_init_from_frame only; other calls return
+ *             DSGM_E_DTYPE
  *   F32X2     compensated single precision (F32/BF16 frames): each state value
  *             is an unevaluated sum hi + lo of two floats (|lo| <= ulp(hi)/2),
  *             stored as interleaved (hi, lo) pairs, 8 bytes per value; every
