@@ -9,7 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+from paper_1702_05156_amd import dsgm
 lib = dsgm.lib
 
 

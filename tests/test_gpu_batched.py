@@ -16,7 +16,7 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+from paper_1702_05156_amd import dsgm
 
 SHAPES = [(40, 16, 64), (3, 8, 8), (120, 4, 256), (1, 1, 4), (17, 24, 32), (64, 32, 128),
           (0, 8, 16), (9, 0, 16), (33, 7, 12), (250, 2, 8)]

@@ -6,7 +6,7 @@ from synth import device as sdev
 
 pytestmark = pytest.mark.gpu
 
-dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+from paper_1702_05156_amd import dsgm
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])

@@ -19,7 +19,7 @@ from tests.test_gpu_forward import _certify_fp32
 
 pytestmark = pytest.mark.gpu
 
-dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+from paper_1702_05156_amd import dsgm
 
 X2 = dsgm.ACC_F32X2
 TOL = 1e-12

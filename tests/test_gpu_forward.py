@@ -17,7 +17,7 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+from paper_1702_05156_amd import dsgm
 
 
 def _run_and_compare(seed, T, H, W, in_dtype=torch.float64, params=None, frames=None):

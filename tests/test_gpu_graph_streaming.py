@@ -16,7 +16,7 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+from paper_1702_05156_amd import dsgm
 
 
 @pytest.mark.parametrize("in_dtype,acc_dtype", [(torch.float64, torch.float64),

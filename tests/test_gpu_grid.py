@@ -12,7 +12,7 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+from paper_1702_05156_amd import dsgm
 
 
 def _run(seed, T, H, W, b, in_dtype=torch.float64, acc_dtype=torch.float64, frames=None,

@@ -19,7 +19,7 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
+from paper_1702_05156_amd import dsgm
 
 # 8192 x 32766 FP64 pixels: 2,147,352,576 bytes per frame, 131,072 under 2^31
 H, W = 8192, 32766

@@ -10,8 +10,8 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-dsgm = pytest.importorskip("paper_1702_05156_amd.dsgm")
-tune = pytest.importorskip("paper_1702_05156_amd.tune")
+from paper_1702_05156_amd import dsgm
+from paper_1702_05156_amd import tune
 
 
 def test_tune_forward_caches_and_applies(tmp_path, monkeypatch):

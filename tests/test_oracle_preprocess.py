@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 
-scipy_ndimage = pytest.importorskip("scipy.ndimage")
+from scipy import ndimage as scipy_ndimage
 
 
 @pytest.mark.parametrize("n,sigma", [(3, 0.8), (5, 1.0), (7, 1.5), (9, 2.0)])

@@ -8,7 +8,7 @@ import pytest
 import oracle
 import synth
 
-ndimage = pytest.importorskip("scipy.ndimage")
+from scipy import ndimage
 
 P = oracle.default_params(2.0)
 
