@@ -129,13 +129,13 @@ __global__ void __launch_bounds__(256) u8_kernel(const FwdArgs a) {
 // lanes walk pixel groups, each lane loading the next group's frame and state
 // bytes before it updates the current group, so the loads of one group overlap
 // the arithmetic of the previous one (with one frame per launch there is no
-// frame loop to hide them behind).  The table is built once per workgroup.
+// frame loop to hide them behind).  The table is built once per workgroup,
+// while the first group's bytes are on their way.  Bounded to 128 VGPRs, so
+// that the whole persistent grid (four workgroups per CU) is resident at once.
 template <int P, bool CODES, bool PRINTED>
-__global__ void __launch_bounds__(256) u8_step_kernel(const FwdArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+u8_step_kernel(const FwdArgs a) {
   __shared__ TableEntry<double> tbl[TABLE_SIZE];
-  fill_table<double>(tbl, a.weight_rule, a.age_max, a.var_init);
-  const StepConsts<double> k =
-      make_consts<double>(a.theta_s, a.theta_d, a.var_init, a.var_floor, a.mask_floor);
   using V = Vec<uint8_t, P>;
   const uint8_t* frame = static_cast<const uint8_t*>(a.frames);
   uint8_t* const planes[4] = {static_cast<uint8_t*>(a.mean_a), static_cast<uint8_t*>(a.var_a),
@@ -160,9 +160,14 @@ __global__ void __launch_bounds__(256) u8_step_kernel(const FwdArgs a) {
   };
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= a.ngroups) return;  // no barrier follows
   Bytes cur, nxt;
-  load(g, cur);
+  // the first group's bytes are requested before the table is built, so their
+  // latency overlaps the table's divisions and its barrier
+  if (g < a.ngroups) load(g, cur);
+  fill_table<double>(tbl, a.weight_rule, a.age_max, a.var_init);
+  const StepConsts<double> k =
+      make_consts<double>(a.theta_s, a.theta_d, a.var_init, a.var_floor, a.mask_floor);
+  if (g >= a.ngroups) return;  // no barrier follows
   for (; g < a.ngroups; g += stride) {
     const bool more = g + stride < a.ngroups;
     if (more) load(g + stride, nxt);
