@@ -92,6 +92,26 @@ def test_u8_one_frame_steps_against_the_oracle(wr, mr, H, W):
         G.assert_bit_exact(k, plane.cpu().numpy().ravel().astype(ref[k].dtype), ref[k])
 
 
+def test_u8_one_frame_steps_full_size_against_the_oracle():
+    """The one-frame kernel as the streaming benchmark runs it (1920 x 2560
+    frames, no codes, the appendix's rules), where every lane of the
+    persistent grid takes several pixel groups in turn: three calls, and the
+    masks of each and the stored state after them equal the 8-bit oracle's."""
+    T, H, W = 3, 1920, 2560
+    x, st = _case(77, T, H, W)
+    p = _params(1, 1)
+    fr = torch.as_tensor(x, device="cuda")
+    s = _dev_state(st, H, W)
+    m = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    for t in range(T):
+        dsgm.dsgm_forward(fr[t:t + 1], s, p, m[t:t + 1])
+    torch.cuda.synchronize()
+    ref = oracle.forward_u8(x.reshape(T, -1), st, G.oracle_params(p), codes=False)
+    G.assert_bit_exact("masks", m.cpu().numpy().reshape(T, -1), ref["masks"])
+    for k, plane in zip(("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"), s.planes()):
+        G.assert_bit_exact(k, plane.cpu().numpy().ravel().astype(ref[k].dtype), ref[k])
+
+
 def test_u8_init_from_frame_and_rejections():
     H, W = 5, 9
     p = _params(1, 1)
