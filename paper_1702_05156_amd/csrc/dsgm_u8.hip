@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(256) u8_init_kernel(const FwdArgs a) {
 // registers while the current one is filtered.  All tile cell indices come
 // from geom::pre::Geo.
 template <int RG, bool MED, bool PRINTED>
-__global__ void __launch_bounds__(256) pre_u8_kernel(const PreArgs a) {
+__global__ void __launch_bounds__(geom::pre::NT) pre_u8_kernel(const PreArgs a) {
   using G = geom::pre::Geo<RG, MED>;
   constexpr int PX = geom::pre::PX, TH = geom::pre::TH, TW = geom::pre::TW;
   constexpr int N = 2 * RG + 1;  // taps per window row
