@@ -51,54 +51,78 @@ __device__ __forceinline__ Pair<Acc> ld_pair(const Acc* p) {
 template <typename In, typename Acc, typename Io>
 __global__ void __launch_bounds__(256) warp_kernel(const WarpArgs a) {
   __shared__ TableEntry<Acc> tbl[TABLE_SIZE];
-  fill_table<Acc>(tbl, a.weight_rule, a.age_max, a.var_init);
-  const StepConsts<Acc> k =
-      make_consts<Acc>(a.theta_s, a.theta_d, a.var_init, a.var_floor, a.mask_floor);
 
   // consecutive rows go to the same XCD, whose L2 then serves the source rows
   // that neighbouring output rows share
   const int64_t i = tile_of(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (i >= a.H * a.W) return;  // no barrier follows
-  const int64_t y = i / a.W, c = i - y * a.W;
+  const bool active = i < a.H * a.W;
+  const int64_t y = active ? i / a.W : 0, c = active ? i - y * a.W : 0;
   const int64_t fo = y * a.row_stride + c;  // frame / output offset
-  const Acc x = to_acc<In, Acc>(static_cast<const In*>(a.frame)[fo]);
 
-  // the source position and its neighbours (dsgm_geom.h)
-  const geom::WarpSrc src = geom::warp_source(c, y, a.map, a.H, a.W);
+  // The frame value, the source position (dsgm_geom.h) and the gathers are
+  // requested before the table is built, so that their latency overlaps the
+  // table's divisions and barrier.  Per state plane, the top and bottom
+  // source rows' two neighbours: one pair load per row at columns xa, xa + 1
+  // (xa = x0 except on the last column, where both neighbours are x0); a
+  // one-column frame loads its single neighbour into both halves.
+  In xin = In();
+  geom::WarpSrc src;
+  src.covered = false;
+  Pair<Acc> top[4], bot[4];
+  bool lo = true;
+  uint8_t age_a = 1, age_c = 1;
+  const Acc* const planes[4] = {static_cast<const Acc*>(a.src_mean_a),
+                                static_cast<const Acc*>(a.src_var_a),
+                                static_cast<const Acc*>(a.src_mean_c),
+                                static_cast<const Acc*>(a.src_var_c)};
+  if (active) {
+    xin = static_cast<const In*>(a.frame)[fo];
+    src = geom::warp_source(c, y, a.map, a.H, a.W);
+    if (src.covered) {
+      if (a.W >= 2) {
+        lo = src.xa == src.x0;
+        const int64_t r0 = src.y0 * a.W + src.xa, r1 = src.y1 * a.W + src.xa;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          top[j] = ld_pair(planes[j] + r0);
+          bot[j] = ld_pair(planes[j] + r1);
+        }
+      } else {
+        const int64_t r0 = src.y0, r1 = src.y1;  // W = 1: x0 = x1 = 0
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const Acc t = planes[j][r0], b = planes[j][r1];
+          top[j] = Pair<Acc>{t, t};
+          bot[j] = Pair<Acc>{b, b};
+        }
+      }
+      age_a = a.src_age_a[src.yn * a.W + src.xn];
+      age_c = a.src_age_c[src.yn * a.W + src.xn];
+    }
+  }
+  fill_table<Acc>(tbl, a.weight_rule, a.age_max, a.var_init);
+  const StepConsts<Acc> k =
+      make_consts<Acc>(a.theta_s, a.theta_d, a.var_init, a.var_floor, a.mask_floor);
+  if (!active) return;  // no barrier follows
+  const Acc x = to_acc<In, Acc>(xin);
+
   Model<Acc> s;
   if (src.covered) {
     const double fx = src.fx, fy = src.fy;
-    const int64_t x0 = src.x0, y0 = src.y0, x1 = src.x1, y1 = src.y1;
     const Acc w00 = Acc((1.0 - fx) * (1.0 - fy)), w10 = Acc(fx * (1.0 - fy));
     const Acc w01 = Acc((1.0 - fx) * fy), w11 = Acc(fx * fy);
-    const Acc* mA = static_cast<const Acc*>(a.src_mean_a);
-    const Acc* vA = static_cast<const Acc*>(a.src_var_a);
-    const Acc* mC = static_cast<const Acc*>(a.src_mean_c);
-    const Acc* vC = static_cast<const Acc*>(a.src_var_c);
-    if (a.W >= 2) {
-      // each row's two neighbours come from one pair load at columns xa, xa+1
-      // (xa = x0 except on the last column, where both neighbours are x0)
-      const int64_t xa = src.xa;
-      const bool lo = xa == x0;
-      const int64_t r0 = y0 * a.W + xa, r1 = y1 * a.W + xa;
-      auto gather = [&](const Acc* p) {
-        const Pair<Acc> t = ld_pair(p + r0), b = ld_pair(p + r1);
-        return bilin(w00, lo ? t.x : t.y, w10, t.y, w01, lo ? b.x : b.y, w11, b.y);
-      };
-      s.mA = gather(mA);
-      s.vA = gather(vA);
-      s.mC = gather(mC);
-      s.vC = gather(vC);
-    } else {
-      const int64_t i00 = y0 * a.W + x0, i10 = y0 * a.W + x1, i01 = y1 * a.W + x0,
-                    i11 = y1 * a.W + x1;
-      s.mA = bilin(w00, mA[i00], w10, mA[i10], w01, mA[i01], w11, mA[i11]);
-      s.vA = bilin(w00, vA[i00], w10, vA[i10], w01, vA[i01], w11, vA[i11]);
-      s.mC = bilin(w00, mC[i00], w10, mC[i10], w01, mC[i01], w11, mC[i11]);
-      s.vC = bilin(w00, vC[i00], w10, vC[i10], w01, vC[i01], w11, vC[i11]);
+    Acc g[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const Pair<Acc> t = top[j], b = bot[j];
+      g[j] = bilin(w00, lo ? t.x : t.y, w10, t.y, w01, lo ? b.x : b.y, w11, b.y);
     }
-    s.aA = a.src_age_a[src.yn * a.W + src.xn];
-    s.aC = a.src_age_c[src.yn * a.W + src.xn];
+    s.mA = g[0];
+    s.vA = g[1];
+    s.mC = g[2];
+    s.vC = g[3];
+    s.aA = age_a;
+    s.aC = age_c;
   } else {
     s.mA = s.mC = x;
     s.vA = s.vC = k.var_init;
