@@ -61,6 +61,34 @@ def test_warped_step_f64_bit_exact(name, H, W):
         G.assert_bit_exact("src " + k, hs0[k], np.asarray(st0[k]).astype(hs0[k].dtype))
 
 
+@pytest.mark.parametrize("k", [0, 1])
+def test_warped_step_full_size_f64_bit_exact(k):
+    """The launch the motion-compensated benchmark times: a 1920 x 2560 FP64
+    frame under one of its homographies (a shift of up to 1.5 pixels and a
+    rotation of up to 0.01 rad, from the same seeded recipe): masks, bg and
+    the new model of every pixel equal the oracle's warp and update."""
+    H, W = 1920, 2560
+    rng = np.random.default_rng(5)
+    for _ in range(k + 1):
+        m = np.eye(3)
+        m[0, 2], m[1, 2] = rng.uniform(-1.5, 1.5, size=2)
+        m[0, 1], m[1, 0] = rng.uniform(-0.01, 0.01, size=2)
+    p = dsgm.dsgm_params_default(2.0)
+    fr, src = G.device_case(1, 1, H, W)
+    dst = dsgm.State.empty(H, W)
+    masks = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    bg = torch.empty((H, W), dtype=torch.float64, device="cuda")
+    dsgm.dsgm_forward_warped(fr[0], src, dst, p, m, masks, bg)
+    torch.cuda.synchronize()
+    x, st0 = G.host_case(1, 1, H, W)
+    ref = _oracle_step(st0, x[0], m, p, H, W)
+    G.assert_bit_exact("masks", masks.cpu().numpy().reshape(1, -1), ref["masks"])
+    G.assert_bit_exact("bg", bg.cpu().numpy().reshape(1, -1), ref["bg"])
+    hs = G.state_to_host(dst)
+    for key in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(key, hs[key], ref[key])
+
+
 @pytest.mark.parametrize("wr,mr", [(1, 0), (0, 1), (1, 1)])
 def test_warped_other_rules_f64_bit_exact(wr, mr):
     """The appendix's weights and its printed mask rule on the motion-compensated
