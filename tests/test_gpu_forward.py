@@ -222,6 +222,28 @@ def test_full_size_f64_sampled_bit_exact():
     del fr, masks
 
 
+def test_streaming_full_size_f64_bit_exact():
+    """One dsgm_forward call per frame, as the streaming benchmark makes them:
+    1920 x 2560 FP64 frames of the structured video (seed 1), three calls
+    from a random mid-run state; every pixel's masks and final state equal
+    the oracle's."""
+    T, H, W, seed = 3, 1920, 2560, 1
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.video(seed, T, H, W, torch.float64)
+    st = dsgm.State(*sdev.state(seed, H, W, torch.float64))
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    for t in range(T):
+        dsgm.dsgm_forward(fr[t:t + 1], st, p, masks[t:t + 1])
+    torch.cuda.synchronize()
+    x = synth.video(seed, T, H, W).reshape(T, -1)
+    st0 = synth.state(seed, H, W, "f64", p.age_max)
+    ref = oracle.forward(x, st0, G.oracle_params(p), bg=False, codes=False)
+    G.assert_bit_exact("masks", masks.cpu().numpy().reshape(T, -1), ref["masks"])
+    hs = G.state_to_host(st)
+    for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+        G.assert_bit_exact(k, hs[k], ref[k])
+
+
 def _certify_fp32(codes_gpu, ref, tol_margin=1e-5):
     """Decision certification for a reduced-precision run.  For every pixel
     whose decision codes differ from the FP64 oracle's, the first differing

@@ -47,6 +47,34 @@ def test_grid_f64_bit_exact(b, T, H, W):
     assert np.array_equal(bg[-1].cpu().numpy().ravel(), ref["mean_a"])
 
 
+def test_grid_full_size_f64_bands_bit_exact():
+    """The launch the grid benchmark times: 1920 x 2560 FP64 frames x 500,
+    seed 1, 4 x 4 blocks, masks only.  Blocks are independent, so two bands
+    of four block rows (the first and the last, every column, all 500
+    frames) are checked exactly against the grid oracle run on those rows."""
+    T, H, W, b, seed = 500, 1920, 2560, 4, 1
+    Hb, Wb = H // b, W // b
+    p = dsgm.dsgm_params_default(2.0)
+    fr = sdev.frames(seed, T, H, W, torch.float64)
+    st = dsgm.State(*sdev.state(seed, Hb, Wb, torch.float64))
+    masks = torch.empty((T, H, W), dtype=torch.uint8, device="cuda")
+    dsgm.dsgm_forward_grid(fr, st, p, b, masks)
+    torch.cuda.synchronize()
+    del fr
+    hs = G.state_to_host(st)
+    for br0 in (0, Hb - 4):
+        rows = np.arange(br0 * b, (br0 + 4) * b)
+        pix = (rows[:, None] * W + np.arange(W)[None, :]).ravel()
+        x = synth.frames(seed, T, H, W, "f64", pix=pix).reshape(T, 4 * b, W)
+        bpix = (np.arange(br0, br0 + 4)[:, None] * Wb + np.arange(Wb)[None, :]).ravel()
+        st0 = synth.state(seed, Hb, Wb, "f64", p.age_max, pix=bpix)
+        ref = oracle.forward_grid(x, st0, G.oracle_params(p), b, codes=False)
+        got = masks[:, rows[0]:rows[-1] + 1, :].cpu().numpy()
+        G.assert_bit_exact(f"masks, block rows {br0}..", got, ref["masks"])
+        for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+            G.assert_bit_exact(f"{k}, block rows {br0}..", hs[k][bpix], ref[k])
+
+
 @pytest.mark.parametrize("b", [1, 4])
 @pytest.mark.parametrize("wr,mr", [(1, 0), (0, 1), (1, 1)])
 def test_grid_other_rules_f64_bit_exact(b, wr, mr):
