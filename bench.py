@@ -780,6 +780,21 @@ def batch_seed(i: int) -> int:
     return 3000 + i
 
 
+def fp64_chunks(shapes, max_bytes=130e9):
+    """The batch's FP64 form in launches that fit: consecutive instances while
+    their FP64 frames stay within max_bytes."""
+    chunks, cur, cur_bytes = [], [], 0
+    for i, (T, H, W) in enumerate(shapes):
+        b = T * H * W * 8
+        if cur and cur_bytes + b > max_bytes:
+            chunks.append(cur)
+            cur, cur_bytes = [], 0
+        cur.append(i)
+        cur_bytes += b
+    chunks.append(cur)
+    return chunks
+
+
 def _batch_items(shapes, idx, dsgm, sdev, torch, frames_dtype, state_dtype, st0):
     """Instances `idx` of the batch: BF16-grid frames stored as `frames_dtype`
     (exact upcast), the FP32 initial state `st0[i]` stored as `state_dtype`."""
@@ -855,15 +870,7 @@ def leg_batched(args, dsgm, sdev, torch):
     torch.cuda.empty_cache()
 
     # the FP64 form, chunked to fit
-    chunks, cur, cur_bytes = [], [], 0
-    for i, (T, H, W) in enumerate(shapes):
-        b = T * H * W * 8
-        if cur and cur_bytes + b > 130e9:
-            chunks.append(cur)
-            cur, cur_bytes = [], 0
-        cur.append(i)
-        cur_bytes += b
-    chunks.append(cur)
+    chunks = fp64_chunks(shapes)
     ms64 = 0.0
     k64 = []
     diff_elems = 0

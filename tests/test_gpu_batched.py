@@ -274,3 +274,41 @@ def test_full_size_batched_sampled():
             G.assert_bit_exact(f"{k}[{i}]", hs[k][pix][clear], ref[k][clear])
     del items, batch, g
     torch.cuda.empty_cache()
+
+
+def test_full_size_batched_fp64_form_chunk_sampled_bit_exact():
+    """The batched benchmark's FP64 form: its first launch (163 instances,
+    129 GB of FP64 frames holding the BF16 values, FP64 state from the FP32
+    initial state, masks and per-frame foreground counts).  For 16 instances
+    (the largest and smallest of the launch and 14 at random) 64 random pixels
+    are replayed by the oracle: masks and final state bit-identical; every
+    instance's counters equal the 255s of its masks."""
+    import bench
+    torch.cuda.empty_cache()
+    shapes = bench.batch_shapes()
+    idx = bench.fp64_chunks(shapes)[0]
+    p = dsgm.dsgm_params_default(2.0)
+    st0 = {i: dsgm.State(*sdev.state(bench.batch_seed(i), shapes[i][1], shapes[i][2], torch.float32))
+           for i in idx}
+    items = bench._batch_items(shapes, idx, dsgm, sdev, torch, torch.float64, torch.float64, st0)
+    dsgm.Batch(items).run(p)
+    torch.cuda.synchronize()
+    assert bench._counts_exact(items, torch)
+    rng = np.random.default_rng(4)
+    sizes = np.array([shapes[i][0] * shapes[i][1] * shapes[i][2] for i in idx])
+    pick = set(rng.choice(len(idx), 14, replace=False).tolist()) | {int(sizes.argmax()), int(sizes.argmin())}
+    op = G.oracle_params(p)
+    for j in sorted(pick):
+        i = idx[j]
+        T, H, W = shapes[i]
+        _, st, masks, _, _ = items[j]
+        pix = np.sort(rng.choice(H * W, 64, replace=False))
+        x, s0 = G.host_case(bench.batch_seed(i), T, H, W, torch.bfloat16, torch.float32, pix=pix)
+        ref = oracle.forward(x, s0, op, bg=False, codes=False)
+        pt = torch.as_tensor(pix, device="cuda")
+        G.assert_bit_exact(f"masks[{i}]", masks.view(T, -1)[:, pt].cpu().numpy(), ref["masks"])
+        hs = G.state_to_host(st)
+        for k in ("mean_a", "var_a", "mean_c", "var_c", "age_a", "age_c"):
+            G.assert_bit_exact(f"{k}[{i}]", hs[k][pix], ref[k])
+    del items, st0
+    torch.cuda.empty_cache()
