@@ -9,9 +9,10 @@
 // registers -- per frame the blend's d = m' - x and a 16-bit word holding the
 // table slot, hitA and swap -- and finally sweeps the chunk backwards, reading
 // the upstream gradient of bg and writing the gradient of the frame.  All of a
-// chunk's frame and gradient loads are issued before its arithmetic, so their
-// HBM latency overlaps.  With K <= KC each frame is replayed once; longer
-// segments replay a prefix per chunk.
+// chunk's frame loads are issued before its replay and its gradient loads
+// before its sweep (with FP64 state during the replay, last frame first, the
+// order the sweep reads them), so their HBM latency overlaps.  With K <= KC
+// each frame is replayed once; longer segments replay a prefix per chunk.
 //
 // The per-pixel contribution to d/d(var_init) is accumulated in FP64 and
 // written to the workspace; reduce_pass1/2 then add the H*W contributions in a
@@ -88,6 +89,16 @@ bwd_kernel(const BwdArgs a) {
 #pragma unroll
     for (int i = 0; i < KC; ++i)
       if (FULL || i < len) xs[i] = *reinterpret_cast<const In*>(frames + (c0 + i) * fs_in + off_in);
+    // the upstream gradients are requested in the order the sweep uses them,
+    // last frame first; with FP32 state those of frames [LATE, KC) after the
+    // replay and [0, LATE) once the sweep reaches frame LATE - 1 (fewer
+    // registers live)
+    constexpr int LATE = sizeof(Acc) == 4 ? KC / 2 : 0;
+    auto load_gb = [&](const int j) {
+      gb[j] = Io(0);
+      if (HAS_GBG && (FULL || j < len))
+        gb[j] = *reinterpret_cast<const Io*>(gbg + (c0 + j) * fs_io + off_io);
+    };
     Acc tape_d[KC];
     uint32_t tape_m[(KC + 1) / 2];
 #pragma unroll
@@ -101,27 +112,20 @@ bwd_kernel(const BwdArgs a) {
         else
           tape_m[i / 2] |= m << 16;
       }
+      // FP64 state: frame i's value is dead now and the gradient the sweep
+      // needs i-th goes out, so the loads overlap the rest of the replay
+      if constexpr (LATE == 0) load_gb(KC - 1 - i);
     }
-    // the gradient loads reuse the frames' registers (dead after the replay);
-    // with FP32 state the frames [LATE, KC) are loaded before the sweep and
-    // [0, LATE) once the sweep reaches frame LATE - 1 (fewer registers live)
-    constexpr int LATE = sizeof(Acc) == 4 ? KC / 2 : 0;
+    if constexpr (LATE > 0) {
 #pragma unroll
-    for (int i = LATE; i < KC; ++i) {
-      gb[i] = Io(0);
-      if (HAS_GBG && (FULL || i < len))
-        gb[i] = *reinterpret_cast<const Io*>(gbg + (c0 + i) * fs_io + off_io);
+      for (int j = KC - 1; j >= LATE; --j) load_gb(j);
     }
 #pragma unroll
     for (int i = KC - 1; i >= 0; --i) {
       if constexpr (LATE > 0) {
         if (i == LATE - 1) {
 #pragma unroll
-          for (int j = 0; j < LATE; ++j) {
-            gb[j] = Io(0);
-            if (HAS_GBG && (FULL || j < len))
-              gb[j] = *reinterpret_cast<const Io*>(gbg + (c0 + j) * fs_io + off_io);
-          }
+          for (int j = LATE - 1; j >= 0; --j) load_gb(j);
         }
       }
       if (FULL || i < len) {
