@@ -87,8 +87,10 @@ __device__ __forceinline__ void fill_table(TableEntry<Acc>* tbl, int weight_rule
 
 // Compile-time variants of the forward kernels.  F_COUNT (batched kernel
 // only) adds the per-frame foreground counts of instances that have counters.
+// F_STEP (one-frame launches without checkpoints or codes) requests the
+// state before the workgroup builds its table.
 enum : int { F_BG = FWD_BG, F_CODES = FWD_CODES, F_CKPT = FWD_CKPT, F_PRINTED = FWD_PRINTED,
-             F_COUNT = 16 };
+             F_COUNT = 16, F_STEP = 32 };
 
 // Everything one lane needs to run its pixel group through T frames.
 struct GroupJob {
@@ -127,16 +129,43 @@ __device__ __forceinline__ void store_state(char* const planes[6], int64_t soff,
   *reinterpret_cast<Vec<uint8_t, P>*>(planes[5] + soff) = aC;
 }
 
+// the group's six state values
+template <typename Acc, int P>
+__device__ __forceinline__ void load_state(const GroupJob& j, Model<Acc>* s) {
+  const int64_t o = j.soff * int64_t(sizeof(Acc));
+  const Vec<Acc, P> mA = *reinterpret_cast<const Vec<Acc, P>*>(j.state[0] + o);
+  const Vec<Acc, P> vA = *reinterpret_cast<const Vec<Acc, P>*>(j.state[1] + o);
+  const Vec<Acc, P> mC = *reinterpret_cast<const Vec<Acc, P>*>(j.state[2] + o);
+  const Vec<Acc, P> vC = *reinterpret_cast<const Vec<Acc, P>*>(j.state[3] + o);
+  const Vec<uint8_t, P> aA = *reinterpret_cast<const Vec<uint8_t, P>*>(j.state[4] + j.soff);
+  const Vec<uint8_t, P> aC = *reinterpret_cast<const Vec<uint8_t, P>*>(j.state[5] + j.soff);
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    s[q].mA = mA.v[q];
+    s[q].vA = vA.v[q];
+    s[q].mC = mC.v[q];
+    s[q].vC = vC.v[q];
+    s[q].aA = aA.v[q];
+    s[q].aC = aC.v[q];
+  }
+}
+
+// The group through its T frames; with F_STEP from the state `pre` the
+// caller has already loaded, else from the state planes.
 template <typename In, typename Acc, typename Io, int P, int U, int FLAGS>
 __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Acc>& k,
-                                          const TableEntry<Acc>* __restrict__ tbl) {
+                                          const TableEntry<Acc>* __restrict__ tbl,
+                                          const Model<Acc>* pre = nullptr) {
   constexpr bool BG = (FLAGS & F_BG) != 0;
   constexpr bool CODES = (FLAGS & F_CODES) != 0;
   constexpr bool CKPT = (FLAGS & F_CKPT) != 0;
   constexpr bool PRINTED = (FLAGS & F_PRINTED) != 0;
   constexpr bool COUNT = (FLAGS & F_COUNT) != 0;
   Model<Acc> s[P];
-  {
+  if constexpr ((FLAGS & F_STEP) != 0) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) s[q] = pre[q];
+  } else {
     const int64_t o = j.soff * int64_t(sizeof(Acc));
     const Vec<Acc, P> mA = *reinterpret_cast<const Vec<Acc, P>*>(j.state[0] + o);
     const Vec<Acc, P> vA = *reinterpret_cast<const Vec<Acc, P>*>(j.state[1] + o);
@@ -250,9 +279,48 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
   store_state<Acc, P>(j.state, j.soff, s);
 }
 
+// The job of one lane group of a one-frame launch (no checkpoints, no codes).
+__device__ __forceinline__ GroupJob step_job(const FwdArgs& a, const geom::Group& G) {
+  GroupJob j;
+  j.frames = static_cast<const char*>(a.frames);
+  j.masks = reinterpret_cast<char*>(a.masks);
+  j.bg = static_cast<char*>(a.bg);
+  j.codes = nullptr;
+  j.state[0] = static_cast<char*>(a.mean_a);
+  j.state[1] = static_cast<char*>(a.var_a);
+  j.state[2] = static_cast<char*>(a.mean_c);
+  j.state[3] = static_cast<char*>(a.var_c);
+  j.state[4] = reinterpret_cast<char*>(a.age_a);
+  j.state[5] = reinterpret_cast<char*>(a.age_c);
+  j.ckpt = nullptr;
+  j.counts = nullptr;
+  j.ckpt_every = 1;
+  j.ckpt_slot_bytes = j.ckpt_fplane = j.ckpt_aplane = 0;
+  j.T = a.T;
+  j.frame_stride = a.frame_stride;
+  j.foff = uint32_t(G.foff);  // < 2^31 elements (host check)
+  j.soff = G.soff;
+  return j;
+}
+
 template <typename In, typename Acc, typename Io, int P, int U, int FLAGS>
 __global__ void __launch_bounds__(256) fwd_kernel(const FwdArgs a) {
   __shared__ TableEntry<Acc> tbl[TABLE_SIZE];
+  if constexpr ((FLAGS & F_STEP) != 0) {
+    // one frame: the state is requested before the table is built, so that
+    // its latency overlaps the table's divisions and barrier
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = g < a.ngroups;
+    const GroupJob j = step_job(a, geom::group_of(g, a.groups_per_row, P, a.W, a.row_stride));
+    Model<Acc> s[P];
+    if (active) load_state<Acc, P>(j, s);
+    fill_table<Acc>(tbl, a.weight_rule, a.age_max, a.var_init);
+    if (!active) return;  // no barrier follows
+    const StepConsts<Acc> k = make_consts<Acc>(a.theta_s, a.theta_d, a.var_init, a.var_floor,
+                                               a.mask_floor);
+    run_group<In, Acc, Io, P, U, FLAGS>(j, k, tbl, s);
+    return;
+  }
   fill_table<Acc>(tbl, a.weight_rule, a.age_max, a.var_init);
 
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -398,6 +466,17 @@ hipError_t launch_fwd_p(const FwdArgs& a, int flags, int block, hipStream_t stre
   }
 }
 
+// one-frame launches without checkpoints or codes (F_STEP)
+template <typename In, typename Acc, typename Io, int P>
+hipError_t launch_fwd_step(const FwdArgs& a, int flags, int block, hipStream_t stream) {
+  switch (flags & (F_BG | F_PRINTED)) {
+    case 0: return launch_fwd_v<In, Acc, Io, P, F_STEP>(a, block, stream);
+    case F_BG: return launch_fwd_v<In, Acc, Io, P, F_STEP | F_BG>(a, block, stream);
+    case F_PRINTED: return launch_fwd_v<In, Acc, Io, P, F_STEP | F_PRINTED>(a, block, stream);
+    default: return launch_fwd_v<In, Acc, Io, P, F_STEP | F_BG | F_PRINTED>(a, block, stream);
+  }
+}
+
 template <typename In, typename Acc, typename Io>
 hipError_t launch_fwd_codes(const FwdArgs& a, int flags, int block, hipStream_t stream) {
   switch (flags & (F_BG | F_CKPT | F_PRINTED)) {
@@ -419,6 +498,11 @@ hipError_t launch_fwd_t(const FwdArgs& a, int P, int flags, int block, hipStream
   if (flags & F_CODES) {
     if (P != 1) return hipErrorInvalidValue;  // the caller sizes the grid for P = 1
     return launch_fwd_codes<In, Acc, Io>(a, flags, block, stream);
+  }
+  if (a.T == 1 && (flags & F_CKPT) == 0) {
+    if (P == 4) return launch_fwd_step<In, Acc, Io, 4>(a, flags, block, stream);
+    if (P == 2) return launch_fwd_step<In, Acc, Io, 2>(a, flags, block, stream);
+    return launch_fwd_step<In, Acc, Io, 1>(a, flags, block, stream);
   }
   if (P == 4) return launch_fwd_p<In, Acc, Io, 4>(a, flags, block, stream);
   if (P == 2) return launch_fwd_p<In, Acc, Io, 2>(a, flags, block, stream);
