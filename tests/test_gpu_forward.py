@@ -156,6 +156,30 @@ def test_streaming_equals_fused():
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("in_dtype,acc_dtype,acc", [
+    (torch.float64, torch.float64, dsgm.ACC_F64), (torch.bfloat16, torch.float32, dsgm.ACC_F32),
+    (torch.float32, torch.float64, dsgm.ACC_F64_IO32)])
+@pytest.mark.parametrize("W", [40, 37])
+@pytest.mark.parametrize("bg,printed", [(False, False), (True, False), (False, True), (True, True)])
+def test_one_frame_calls_equal_the_fused_call(in_dtype, acc_dtype, acc, W, bg, printed):
+    """One-frame calls without checkpoints or codes run their own kernel
+    variant: frame by frame it gives the masks, bg and state of one call over
+    all frames, for every output and mask-rule variant, at the widest pixels
+    per lane the type allows (W = 40) and at one (W = 37)."""
+    T, H = 12, 9
+    p = dsgm.dsgm_params_default(2.0, dsgm.MASK_PRINTED if printed else dsgm.MASK_VARIANCE)
+    fr, st = G.device_case(21, T, H, W, in_dtype, acc_dtype)
+    st2 = st.clone()
+    fused = dsgm.forward(fr, st, p, bg=bg, acc=acc)
+    for t in range(T):
+        one = dsgm.forward(fr[t:t + 1], st2, p, bg=bg, acc=acc)
+        assert torch.equal(one["masks"][0], fused["masks"][t]), t
+        if bg:
+            assert torch.equal(one["bg"][0], fused["bg"][t]), t
+    for a, b in zip(st.planes(), st2.planes()):
+        assert torch.equal(a, b)
+
+
 def test_checkpoints_hold_the_oracle_state():
     T, H, W, K = 45, 6, 32, 8
     p = dsgm.dsgm_params_default(2.0)
