@@ -166,6 +166,9 @@ __device__ __forceinline__ void run_group(const GroupJob& j, const StepConsts<Ac
 #pragma unroll
     for (int q = 0; q < P; ++q) s[q] = pre[q];
   } else {
+    // load_state's loads written out rather than called: a call compiles
+    // the time-fused kernels to a different instruction schedule than the
+    // one their measurements were made with
     const int64_t o = j.soff * int64_t(sizeof(Acc));
     const Vec<Acc, P> mA = *reinterpret_cast<const Vec<Acc, P>*>(j.state[0] + o);
     const Vec<Acc, P> vA = *reinterpret_cast<const Vec<Acc, P>*>(j.state[1] + o);
